@@ -1,0 +1,90 @@
+"""CPU oracle for connected-components labeling -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never calls it and
+shares no code with it.
+
+The arithmetic lives in ``ccl_oracle.c`` (a plain single-threaded flood
+fill, compiled with gcc).  This module only compiles it and marshals numpy
+arrays through ctypes.
+
+Definition computed (Introduction; Sec. II-A-2 and the atomicMin merge of
+Sec. II-A-3, which make every root the smallest index of its set):
+
+    label[y, x] = 0                                   for background
+    label[y, x] = 1 + min raster index (y' * W + x')  over the component
+
+Parity pins: the tests check this against a brute-force transitive closure
+on every tiny image, against ``scipy.ndimage.label`` after renumbering, and
+against closed forms of hand-built patterns.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ccl_oracle.c")
+_LIB = os.path.join(_HERE, "libccl_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/libccl_oracle.so``."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-Wall", "-Werror", _SRC, "-o", tmp]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _get():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        for name in ("oracle_label_2d", "oracle_label_2d_equal"):
+            fn = getattr(lib, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                           ctypes.c_int, ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+def _run2d(name: str, img: np.ndarray, conn: int) -> np.ndarray:
+    img = np.asarray(img)
+    if img.ndim != 2:
+        raise ValueError("expected a 2D image")
+    if img.dtype != np.uint8:
+        raise ValueError("expected uint8 pixels")
+    if img.strides[1] != 1:
+        img = np.ascontiguousarray(img)
+    H, W = img.shape
+    out = np.empty((H, W), dtype=np.uint32)
+    if H == 0 or W == 0:
+        return out
+    # numpy may report any stride for a dimension of extent 1
+    pitch = img.strides[0] if H > 1 else W
+    if pitch < W:
+        img = np.ascontiguousarray(img)
+        pitch = W
+    rc = getattr(_get(), name)(img.ctypes.data, H, W, pitch, int(conn), out.ctypes.data)
+    if rc != 0:
+        raise ValueError("%s failed with code %d (H=%d W=%d conn=%r)" % (name, rc, H, W, conn))
+    return out
+
+
+def label(img: np.ndarray, conn: int = 8) -> np.ndarray:
+    """Canonical binary labels: nonzero pixels are foreground, background is 0."""
+    return _run2d("oracle_label_2d", img, conn)
+
+
+def label_equal(img: np.ndarray, conn: int = 8) -> np.ndarray:
+    """Labels of every equal-value class (background included): 1 + min raster index."""
+    return _run2d("oracle_label_2d_equal", img, conn)

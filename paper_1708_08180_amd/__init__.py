@@ -1,0 +1,15 @@
+"""MI355X-native union-find connected-components labeling (three phases:
+tile-local merge, boundary analysis on tile-edge cells, link).
+
+The arithmetic runs in hand-written HIP kernels for gfx950 inside
+``libccl.so``; this package only marshals arguments to its C ABI.  The
+library is loaded on first use; a missing or unbuilt library raises
+``RuntimeError`` -- there is no CPU fallback.
+"""
+from .binding import (  # noqa: F401
+    CclError,
+    label,
+    label_batch,
+    library_path,
+    load_library,
+)
