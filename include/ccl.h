@@ -1,0 +1,127 @@
+/*
+ * ccl.h -- C ABI of libccl, union-find connected-components labeling of 2D
+ * binary images on AMD Instinct MI355X (gfx950).
+ *
+ * Method: the three phases of Chen et al., "An Optimized Union-Find
+ * Algorithm for Connected Components Labeling Using GPUs" (arXiv 1708.08180):
+ *   1. local union-find merge with coarse (row-run) labeling inside each tile
+ *      (Sec. II-A, Kernel 1),
+ *   2. boundary analysis that runs union-find only on tile-edge cells
+ *      (Sec. II-B, Kernel 2, Eqs. (1)-(2)),
+ *   3. link: every pixel is resolved to the root of its tree (Sec. II-C).
+ *
+ * Output contract (every entry point): labels[y*W + x] = 0 for a background
+ * pixel (value 0); for a foreground pixel (any nonzero value) it is 1 plus
+ * the smallest raster index y'*W + x' over the pixel's connected component.
+ * The merge always links the larger index under the smaller (Sec. II-A-3),
+ * so the root of every component is its smallest index; the +1 keeps 0 free
+ * for background.  Raster indices use the width W, never the row pitch.
+ * The labeling is unique, so results are bit-exact and deterministic.
+ *
+ * Conventions
+ *   - Pointers named img/labels/workspace are DEVICE pointers (hipMalloc or
+ *     equivalent) unless stated; descriptor arrays are HOST pointers.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued asynchronously; the caller synchronizes.
+ *   - Every entry point validates all arguments before enqueuing anything
+ *     and returns a ccl_status.  No exception crosses the ABI.
+ *   - img and labels must not overlap.  The caller owns all buffers it
+ *     passes; the library never frees them.
+ *   - The contents of `labels` on entry are ignored; the buffer is fully
+ *     overwritten.  It also serves as the union-find forest while the call
+ *     runs, so it must not be read until the work on `stream` completes.
+ */
+#ifndef CCL_H_
+#define CCL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ccl_status {
+    CCL_OK = 0,
+    CCL_ERR_INVALID_ARG = 1,  /* null pointer, H or W <= 0, pitch < W, n < 0, bad option */
+    CCL_ERR_UNSUPPORTED = 2,  /* connectivity not in {4, 8}, unsupported tile config */
+    CCL_ERR_TOO_LARGE = 3,    /* H*W > 2^32 - 1: a label would overflow uint32 */
+    CCL_ERR_HIP = 4,          /* a HIP runtime call or launch failed; see ccl_last_hip_error */
+    CCL_ERR_OUT_OF_MEMORY = 5,/* a workspace allocation failed */
+    CCL_ERR_CAPACITY = 6,     /* a batch exceeds the context's fixed capacity */
+    CCL_ERR_WORKSPACE = 7     /* a caller-supplied workspace is too small */
+} ccl_status;
+
+/* Tile configuration of the three kernels.  A tile is 64 pixels wide (one
+ * 64-lane wavefront spans a tile row) and tile_h rows tall; each workgroup
+ * runs `waves` wavefronts, each owning tile_h / waves consecutive rows.
+ * Supported pairs: tile_h in {16, 32, 64}; waves in {1, 2, 4, 8, 16} with
+ * waves <= tile_h.  A zeroed struct or a NULL pointer selects the default. */
+typedef struct ccl_config {
+    int32_t tile_h;
+    int32_t waves;
+} ccl_config;
+
+/* Human-readable name of a status code (static storage; never NULL). */
+const char *ccl_status_string(int status);
+
+/* hipError_t of the most recent CCL_ERR_HIP on the calling thread (0 if none). */
+int ccl_last_hip_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int ccl_version(void);
+
+/*
+ * ccl_label_2d -- label one 2D binary image (Secs. II-A to II-C).
+ *
+ * img     device pointer to H rows of `pitch` bytes; pixel (y, x) is
+ *         img[y*pitch + x]; nonzero = foreground.
+ * H, W    image height and width in pixels, both >= 1, H*W <= 2^32 - 1.
+ * pitch   row stride of img in bytes, pitch >= W.
+ * connectivity  4 (edge neighbours, the paper's Kernel 1) or 8 (edge and
+ *         corner neighbours).
+ * labels  device pointer to a dense H*W uint32 array (row stride W),
+ *         written as described at the top of this file.
+ * stream  hipStream_t (void*), NULL for the null stream.
+ *
+ * Scratch: a small per-(device, stream) workspace (about 4.2 bytes per
+ * pixel / 64 for the default tiles) is allocated on first use and grown
+ * when a larger image arrives on the same stream (growth synchronizes that
+ * stream before freeing the old buffer); ccl_shutdown releases it.  Two
+ * concurrent calls on the same stream are ordered by the stream; calls on
+ * different streams use different workspaces.
+ * Returns CCL_OK or an error; on error nothing has been enqueued (except
+ * CCL_ERR_HIP from a failed launch).
+ */
+int ccl_label_2d(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
+                 int32_t connectivity, uint32_t *labels, void *stream);
+
+/* Bytes of workspace ccl_label_2d_ex needs for an H x W image with tile
+ * configuration cfg (NULL = default).  Writes *bytes; returns a status. */
+int ccl_workspace_size(int32_t H, int32_t W, const ccl_config *cfg, size_t *bytes);
+
+/*
+ * ccl_label_2d_ex -- as ccl_label_2d, with an explicit tile configuration
+ * and an optional caller-owned workspace.
+ *
+ * workspace, workspace_bytes  device buffer of at least
+ *         ccl_workspace_size(H, W, cfg) bytes, 256-byte aligned, not in
+ *         use by any other call until this call's work on `stream` has
+ *         completed.  NULL selects the library's per-stream workspace.
+ *         Too small: CCL_ERR_WORKSPACE.
+ * cfg     tile configuration, NULL or zeroed = default.  Unsupported
+ *         pairs return CCL_ERR_UNSUPPORTED.
+ */
+int ccl_label_2d_ex(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
+                    int32_t connectivity, uint32_t *labels, void *workspace,
+                    size_t workspace_bytes, const ccl_config *cfg, void *stream);
+
+/* Release every workspace the library allocated (all devices) after
+ * synchronizing the devices that own them.  Later calls allocate again. */
+void ccl_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCL_H_ */

@@ -1,7 +1,178 @@
-# placeholder, replaced below
+"""ctypes binding of libccl's C ABI (argument marshalling only).
+
+Every labeling step runs in the HIP kernels inside ``libccl.so``; torch is
+used here only to own device memory and to name the current HIP stream.
+If the library has not been built, every call raises ``CclError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(PKG, "libccl.so")
+_lib = None
+_lock = threading.Lock()
+
+CCL_OK = 0
+
+
 class CclError(RuntimeError):
-    pass
-def label(*a, **k): raise CclError("not built")
-def label_batch(*a, **k): raise CclError("not built")
-def library_path(): return None
-def load_library(): raise CclError("not built")
+    def __init__(self, msg, status=None):
+        super().__init__(msg)
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("tile_h", ctypes.c_int32), ("waves", ctypes.c_int32)]
+
+
+class ImageDesc(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("labels", ctypes.c_void_p), ("H", ctypes.c_int32),
+                ("W", ctypes.c_int32), ("pitch", ctypes.c_int64)]
+
+
+class CtxOpts(ctypes.Structure):
+    _fields_ = [("max_images", ctypes.c_int32), ("max_tiles", ctypes.c_int64),
+                ("tile_h", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+
+# name -> (restype, argtypes); every symbol include/ccl.h declares
+SIGNATURES = {
+    "ccl_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ccl_last_hip_error": (ctypes.c_int, []),
+    "ccl_version": (ctypes.c_int, []),
+    "ccl_label_2d": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, _P]),
+    "ccl_workspace_size": (ctypes.c_int, [_I32, _I32, ctypes.POINTER(Config),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "ccl_label_2d_ex": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, _P, ctypes.c_size_t,
+                                       ctypes.POINTER(Config), _P]),
+    "ccl_shutdown": (None, []),
+}
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libccl.so once; raise CclError if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH):
+            raise CclError("libccl.so is not built (expected at %s); run __graft_entry__.build()"
+                           % _LIB_PATH)
+        lib = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != CCL_OK:
+        lib = load_library()
+        msg = lib.ccl_status_string(rc).decode()
+        if rc == 4:
+            msg += " (hipError %d)" % lib.ccl_last_hip_error()
+        raise CclError("%s failed: %s" % (what, msg), rc)
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _pitch(img) -> int:
+    H, W = img.shape
+    return int(img.stride(0)) if H > 1 else int(W)
+
+
+def _check_image(img):
+    torch = _torch()
+    if not isinstance(img, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if img.dim() != 2:
+        raise ValueError("expected a 2D image, got shape %s" % (tuple(img.shape),))
+    if img.dtype != torch.uint8:
+        raise ValueError("expected uint8 pixels, got %s" % img.dtype)
+    if not img.is_cuda:
+        raise ValueError("image must be a device (cuda) tensor")
+    if img.shape[1] > 1 and img.stride(1) != 1:
+        raise ValueError("image rows must be contiguous (stride(1) == 1)")
+
+
+def label(img, conn: int = 8, out=None, config=None, stream=None, workspace=None):
+    """Label a 2D uint8 device image; returns an int32 tensor holding the
+    uint32 labels bit for bit (0 = background, else 1 + min raster index)."""
+    torch = _torch()
+    _check_image(img)
+    H, W = img.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.int32, device=img.device)
+    else:
+        if out.shape != (H, W) or out.dtype != torch.int32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 tensor of shape (H, W)")
+    lib = load_library()
+    cfg = None
+    if config is not None:
+        cfg = ctypes.byref(Config(int(config[0]), int(config[1])))
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    with torch.cuda.device(img.device):
+        rc = lib.ccl_label_2d_ex(img.data_ptr(), H, W, _pitch(img), int(conn), out.data_ptr(),
+                                 ws_ptr, ws_bytes, cfg, _stream_handle(stream))
+    _check(rc, "ccl_label_2d_ex")
+    return out
+
+
+def label_plain(img, conn: int = 8, out=None, stream=None):
+    """The plain ccl_label_2d entry point (library-owned workspace, default tiles)."""
+    torch = _torch()
+    _check_image(img)
+    H, W = img.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.int32, device=img.device)
+    lib = load_library()
+    with torch.cuda.device(img.device):
+        rc = lib.ccl_label_2d(img.data_ptr(), H, W, _pitch(img), int(conn), out.data_ptr(),
+                              _stream_handle(stream))
+    _check(rc, "ccl_label_2d")
+    return out
+
+
+def workspace_size(H: int, W: int, config=None) -> int:
+    lib = load_library()
+    n = ctypes.c_size_t(0)
+    cfg = ctypes.byref(Config(int(config[0]), int(config[1]))) if config else None
+    _check(lib.ccl_workspace_size(int(H), int(W), cfg, ctypes.byref(n)), "ccl_workspace_size")
+    return int(n.value)
+
+
+def shutdown():
+    load_library().ccl_shutdown()
+
+
+def label_batch(*args, **kwargs):
+    raise CclError("label_batch is not available in this build")

@@ -1,0 +1,182 @@
+// C ABI of libccl: argument validation, tile-configuration choice, the
+// per-stream workspace cache and the single-image entry points.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "ccl.h"
+#include "ccl_internal.h"
+
+namespace ccl {
+
+static thread_local int g_last_hip_error = 0;
+
+int fail_hip(hipError_t e) {
+    g_last_hip_error = (int)e;
+    return CCL_ERR_HIP;
+}
+
+// Default tile configuration.  The tuning table (ccl_tune.cpp) may override
+// it per size class and connectivity.
+void default_config(int H, int W, int conn, int *th, int *nw);
+
+namespace {
+
+struct WsEntry {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, WsEntry> g_ws;
+
+// Workspace owned by the library for (current device, stream); grown on
+// demand.  Growth synchronizes the stream before releasing the old buffer
+// because earlier work on that stream may still read it.
+int stream_workspace(hipStream_t s, size_t need, void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    WsEntry &w = g_ws[std::make_pair(dev, s)];
+    if (w.bytes < need) {
+        if (w.ptr) {
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return fail_hip(e);
+            (void)hipFree(w.ptr);
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+        size_t bytes = need + need / 4;  // headroom so slowly growing sizes do not reallocate
+        e = hipMalloc(&w.ptr, bytes);
+        if (e != hipSuccess) {
+            w.ptr = nullptr;
+            (void)hipGetLastError();
+            return CCL_ERR_OUT_OF_MEMORY;
+        }
+        w.bytes = bytes;
+    }
+    *out = w.ptr;
+    return CCL_OK;
+}
+
+}  // namespace
+
+void release_stream_workspaces() {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (auto &kv : g_ws) {
+        if (!kv.second.ptr) continue;
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(kv.first.first);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(kv.second.ptr);
+        (void)hipSetDevice(prev);
+    }
+    g_ws.clear();
+}
+
+int validate_image(const void *img, int32_t H, int32_t W, int64_t pitch, const void *labels) {
+    if (!img || !labels) return CCL_ERR_INVALID_ARG;
+    if (H <= 0 || W <= 0 || pitch < (int64_t)W) return CCL_ERR_INVALID_ARG;
+    if ((uint64_t)H * (uint64_t)W > 0xFFFFFFFFull) return CCL_ERR_TOO_LARGE;
+    return CCL_OK;
+}
+
+int resolve_config(int H, int W, int conn, const ccl_config *cfg, int *th, int *nw) {
+    if (cfg && (cfg->tile_h != 0 || cfg->waves != 0)) {
+        if (!config_supported(cfg->tile_h, cfg->waves)) return CCL_ERR_UNSUPPORTED;
+        *th = cfg->tile_h;
+        *nw = cfg->waves;
+        return CCL_OK;
+    }
+    default_config(H, W, conn, th, nw);
+    return CCL_OK;
+}
+
+ImgView make_view(const uint8_t *img, int32_t H, int32_t W, int64_t pitch, uint32_t *labels,
+                  void *ws, int th) {
+    const WsLayout l = ws_layout(H, W, th);
+    ImgView v;
+    v.img = img;
+    v.labels = labels;
+    v.masks = (uint64_t *)ws;
+    v.roots = (uint32_t *)((char *)ws + l.mask_bytes);
+    v.pitch = pitch;
+    v.H = H;
+    v.W = W;
+    v.tilesX = (W + kTileW - 1) / kTileW;
+    v.tilesY = (H + th - 1) / th;
+    v.n = (uint32_t)((uint64_t)H * (uint64_t)W);
+    return v;
+}
+
+}  // namespace ccl
+
+using namespace ccl;
+
+extern "C" {
+
+const char *ccl_status_string(int status) {
+    switch (status) {
+        case CCL_OK: return "CCL_OK";
+        case CCL_ERR_INVALID_ARG: return "CCL_ERR_INVALID_ARG: invalid argument";
+        case CCL_ERR_UNSUPPORTED: return "CCL_ERR_UNSUPPORTED: unsupported connectivity or configuration";
+        case CCL_ERR_TOO_LARGE: return "CCL_ERR_TOO_LARGE: H*W exceeds 2^32-1";
+        case CCL_ERR_HIP: return "CCL_ERR_HIP: HIP runtime error";
+        case CCL_ERR_OUT_OF_MEMORY: return "CCL_ERR_OUT_OF_MEMORY: workspace allocation failed";
+        case CCL_ERR_CAPACITY: return "CCL_ERR_CAPACITY: batch exceeds context capacity";
+        case CCL_ERR_WORKSPACE: return "CCL_ERR_WORKSPACE: workspace too small";
+        default: return "unknown ccl status";
+    }
+}
+
+int ccl_last_hip_error(void) { return g_last_hip_error; }
+
+int ccl_version(void) { return 10000; }
+
+int ccl_workspace_size(int32_t H, int32_t W, const ccl_config *cfg, size_t *bytes) {
+    if (!bytes || H <= 0 || W <= 0) return CCL_ERR_INVALID_ARG;
+    if ((uint64_t)H * (uint64_t)W > 0xFFFFFFFFull) return CCL_ERR_TOO_LARGE;
+    int th = 0, nw = 0;
+    const int rc = resolve_config(H, W, 8, cfg, &th, &nw);
+    if (rc != CCL_OK) return rc;
+    *bytes = ws_layout(H, W, th).total;
+    return CCL_OK;
+}
+
+int ccl_label_2d_ex(const uint8_t *img, int32_t H, int32_t W, int64_t pitch, int32_t connectivity,
+                    uint32_t *labels, void *workspace, size_t workspace_bytes,
+                    const ccl_config *cfg, void *stream) {
+    int rc = validate_image(img, H, W, pitch, labels);
+    if (rc != CCL_OK) return rc;
+    if (connectivity != 4 && connectivity != 8) return CCL_ERR_UNSUPPORTED;
+    int th = 0, nw = 0;
+    rc = resolve_config(H, W, connectivity, cfg, &th, &nw);
+    if (rc != CCL_OK) return rc;
+    const size_t need = ws_layout(H, W, th).total;
+    hipStream_t s = (hipStream_t)stream;
+    void *ws = workspace;
+    if (ws) {
+        if (workspace_bytes < need) return CCL_ERR_WORKSPACE;
+        if (((uintptr_t)ws & 255u) != 0) return CCL_ERR_INVALID_ARG;
+    } else {
+        rc = stream_workspace(s, need, &ws);
+        if (rc != CCL_OK) return rc;
+    }
+    const ImgView v = make_view(img, H, W, pitch, labels, ws, th);
+    const hipError_t e = launch_plain(v, th, nw, connectivity, s);
+    if (e != hipSuccess) return fail_hip(e);
+    return CCL_OK;
+}
+
+int ccl_label_2d(const uint8_t *img, int32_t H, int32_t W, int64_t pitch, int32_t connectivity,
+                 uint32_t *labels, void *stream) {
+    return ccl_label_2d_ex(img, H, W, pitch, connectivity, labels, nullptr, 0, nullptr, stream);
+}
+
+void ccl_shutdown(void) { release_stream_workspaces(); }
+
+}  // extern "C"
