@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Benchmark of the three-phase union-find CCL on one MI355X.
+
+Default workload: one 4096 x 4096 uint8 image, Bernoulli(p = 0.5) pixels
+(seeded), 8-connectivity, uint32 canonical labels.  A step is one full
+ccl_label_2d call (local merge, boundary analysis, link) on the image
+already resident in HBM; K steps run back to back on one stream between
+two synchronizations and are timed with HIP events.
+
+Prints ONE JSON line with the throughput (Gpixels/s), the roofline of the
+dominant kernel (per-phase HIP events over a second timed pass), and the
+CPU oracle timed on the host as a reported baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       [--workload headline|sweep|structured] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+BYTES_PER_PIXEL_PATH = 5        # algorithmic minimum: 1 B image in + 4 B label out
+PAPER_CONTEXT = {"gpix_s": 4.99, "ms": 3.36, "hardware": "NVIDIA GTX 1070",
+                 "image": "binarized lena 4096x4096", "source": "Table II"}
+
+# algorithmic bytes per pixel of each phase (what the phase must move at least)
+PHASE_NAMES = ("k1_local_merge", "k2_boundary", "k3_link")
+PHASE_BYTES_PER_PIXEL = (1.0, 0.0, 5.0)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1708_08180_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    only if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = data.get("%s@%s" % (kernel, workload))
+    if not ent or ent.get("source_digest") != kernel_source_digest():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def time_calls(lib, args_for_call, steps, stream_handle, torch):
+    """K back-to-back calls bracketed by events on the work stream."""
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        rc = lib.ccl_label_2d(*args_for_call)
+        if rc != 0:
+            raise RuntimeError("ccl_label_2d failed: %d" % rc)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(end), wall
+
+
+def per_call_times(lib, call_args, n, torch):
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record(stream)
+        lib.ccl_label_2d(*call_args)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
+
+
+def cpu_baseline(img, conn, gpu_labels, seconds):
+    import numpy as np
+
+    import oracle
+
+    reps, t_total, want = 0, 0.0, None
+    while reps < 1 or t_total < seconds:
+        t0 = time.perf_counter()
+        want = oracle.label(img, conn)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    px = img.shape[0] * img.shape[1]
+    parity = bool(np.array_equal(gpu_labels, want))
+    return {"value": round(px * reps / t_total / 1e9, 5), "unit": "Gpixels/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d full %dx%d conn-%d labelings, single-threaded C flood fill (%.1f s)"
+                      % (reps, img.shape[0], img.shape[1], conn, t_total),
+            "parity_vs_gpu": parity}
+
+
+def make_workload(name):
+    from paper_1708_08180_amd import workloads as wl
+
+    if name == "headline":
+        return [("bernoulli p=0.5 g=1", wl.bernoulli(4096, 4096, 0.5, wl.sweep_seed(0.5, 1), 1))]
+    if name == "sweep":
+        return [("bernoulli p=%.1f g=%d" % (p, g), wl.bernoulli(4096, 4096, p, wl.sweep_seed(p, g), g))
+                for p in wl.SWEEP_P for g in wl.SWEEP_G]
+    if name == "structured":
+        return [("smoothed sigma=4", wl.smoothed_noise(8192, 8192, 4.0, 30001)),
+                ("serpentine", wl.serpentine(8192, 8192)),
+                ("spiral", wl.spiral(8192, 8192))]
+    raise SystemExit("unknown workload %s" % name)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--conn", type=int, default=8, choices=(4, 8))
+    ap.add_argument("--workload", default="headline", choices=("headline", "sweep", "structured"))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--config", default=None, help="tile_h,waves (default: library choice)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU; --gpus %d (WORLD_SIZE=%d) is not supported. "
+              "Images are independent, so several GPUs would each label their own images; "
+              "see the sharding notes in the design document." % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1708_08180_amd import binding
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    lib = binding.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    cfg = None
+    if args.config:
+        th, nw = (int(v) for v in args.config.split(","))
+        cfg = binding.Config(th, nw)
+
+    results = []
+    for name, img in make_workload(args.workload):
+        H, W = img.shape
+        d_img = torch.from_numpy(img).to(dev)
+        d_lab = torch.empty((H, W), dtype=torch.int32, device=dev)
+        if cfg is None:
+            call = (d_img.data_ptr(), H, W, W, args.conn, d_lab.data_ptr(), sh)
+            call_fn = lib.ccl_label_2d
+        else:
+            call = (d_img.data_ptr(), H, W, W, args.conn, d_lab.data_ptr(), None, 0, ctypes.byref(cfg), sh)
+            call_fn = lib.ccl_label_2d_ex
+
+        class _L:  # route time_calls through the chosen entry point
+            ccl_label_2d = staticmethod(call_fn)
+
+        for _ in range(args.warmup):
+            call_fn(*call)
+        torch.cuda.synchronize()
+        log("[bench] %s %dx%d conn=%d: warmup done" % (name, H, W, args.conn))
+        ms_total, wall = time_calls(_L, call, args.steps, sh, torch)
+        ms = ms_total / args.steps
+        log("[bench] %s: %.4f ms/step (wall %.3f s)" % (name, ms, wall))
+        calls = per_call_times(_L, call, min(100, args.steps), torch)
+        phase = np.zeros(3)
+        n_ph = min(100, args.steps)
+        for _ in range(n_ph):
+            _, ph = binding.label_timed(d_img, args.conn, out=d_lab,
+                                        config=(cfg.tile_h, cfg.waves) if cfg else None)
+            phase += np.array(ph)
+        phase /= n_ph
+        labels = d_lab.cpu().numpy().view(np.uint32)
+        results.append(dict(name=name, img=img, H=H, W=W, ms=ms, wall=wall, calls=calls,
+                            phase=phase.tolist(), labels=labels))
+        del d_img, d_lab
+
+    head = results[0]
+    px = head["H"] * head["W"]
+    gpix = px / (head["ms"] * 1e-3) / 1e9
+    k = int(np.argmax(head["phase"]))
+    t_k = head["phase"][k] * 1e-3
+    alg = PHASE_BYTES_PER_PIXEL[k] * px
+    achieved = alg / t_k / 1e9
+    roofline = {"bound": "hbm", "kernel": PHASE_NAMES[k], "achieved": round(achieved, 2),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": stored_traffic(PHASE_NAMES[k], "4096x4096-bern0.5-conn%d" % args.conn),
+                "alg_bytes_per_launch": int(alg),
+                "kernel_ms": round(head["phase"][k], 5)}
+    path_gbs = BYTES_PER_PIXEL_PATH * px / (head["ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "Gpixels/s (4096^2 8-conn) & % HBM roofline",
+        "value": round(gpix, 3),
+        "unit": "Gpixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "%dx%d uint8 Bernoulli(p=0.5) g=1 seed=%d, %d-connectivity, uint32 labels"
+                               % (head["H"], head["W"], 20000 + 100 * 5 + 1, args.conn),
+                   "tile": (args.config or "library default")},
+        "roofline": roofline,
+        "path_hbm": {"alg_bytes_per_pixel": BYTES_PER_PIXEL_PATH, "achieved_GBs": round(path_gbs, 2),
+                     "frac": round(path_gbs / HBM_PEAK_GBS, 4)},
+        "phase_ms": {n: round(v, 5) for n, v in zip(PHASE_NAMES, head["phase"])},
+        "per_call_ms": {"min": round(min(head["calls"]), 5), "mean": round(statistics.mean(head["calls"]), 5),
+                        "median": round(statistics.median(head["calls"]), 5),
+                        "max": round(max(head["calls"]), 5), "n": len(head["calls"])},
+        "paper_context": PAPER_CONTEXT,
+    }
+    if len(results) > 1:
+        rates = [r["H"] * r["W"] / (r["ms"] * 1e-3) / 1e9 for r in results]
+        out["workload_set"] = {"name": args.workload, "n": len(results),
+                               "gpix_min": round(min(rates), 3),
+                               "gpix_median": round(statistics.median(rates), 3),
+                               "gpix_max": round(max(rates), 3),
+                               "cells": {r["name"]: round(v, 3) for r, v in zip(results, rates)}}
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on the host (about %.0f s)" % args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(head["img"], args.conn, head["labels"], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -53,6 +53,8 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_size_t)]),
     "ccl_label_2d_ex": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, _P, ctypes.c_size_t,
                                        ctypes.POINTER(Config), _P]),
+    "ccl_label_2d_timed": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, ctypes.POINTER(Config), _P,
+                                          ctypes.POINTER(ctypes.c_float)]),
     "ccl_shutdown": (None, []),
 }
 
@@ -160,6 +162,23 @@ def label_plain(img, conn: int = 8, out=None, stream=None):
                               _stream_handle(stream))
     _check(rc, "ccl_label_2d")
     return out
+
+
+def label_timed(img, conn: int = 8, out=None, config=None, stream=None):
+    """Label and return (labels, [ms_phase1, ms_phase2, ms_phase3]); blocks."""
+    torch = _torch()
+    _check_image(img)
+    H, W = img.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.int32, device=img.device)
+    lib = load_library()
+    cfg = ctypes.byref(Config(int(config[0]), int(config[1]))) if config else None
+    ms = (ctypes.c_float * 3)()
+    with torch.cuda.device(img.device):
+        rc = lib.ccl_label_2d_timed(img.data_ptr(), H, W, _pitch(img), int(conn), out.data_ptr(),
+                                    cfg, _stream_handle(stream), ms)
+    _check(rc, "ccl_label_2d_timed")
+    return out, [float(ms[0]), float(ms[1]), float(ms[2])]
 
 
 def workspace_size(H: int, W: int, config=None) -> int:

@@ -177,6 +177,35 @@ int ccl_label_2d(const uint8_t *img, int32_t H, int32_t W, int64_t pitch, int32_
     return ccl_label_2d_ex(img, H, W, pitch, connectivity, labels, nullptr, 0, nullptr, stream);
 }
 
+int ccl_label_2d_timed(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
+                       int32_t connectivity, uint32_t *labels, const ccl_config *cfg,
+                       void *stream, float *phase_ms) {
+    if (!phase_ms) return CCL_ERR_INVALID_ARG;
+    int rc = validate_image(img, H, W, pitch, labels);
+    if (rc != CCL_OK) return rc;
+    if (connectivity != 4 && connectivity != 8) return CCL_ERR_UNSUPPORTED;
+    int th = 0, nw = 0;
+    rc = resolve_config(H, W, connectivity, cfg, &th, &nw);
+    if (rc != CCL_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    void *ws = nullptr;
+    rc = stream_workspace(s, ws_layout(H, W, th).total, &ws);
+    if (rc != CCL_OK) return rc;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    if (e == hipSuccess) {
+        const ImgView v = make_view(img, H, W, pitch, labels, ws, th);
+        e = launch_plain(v, th, nw, connectivity, s, ev);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventElapsedTime(&phase_ms[i], ev[i], ev[i + 1]);
+    for (int i = 0; i < 4; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (e != hipSuccess) return fail_hip(e);
+    return CCL_OK;
+}
+
 void ccl_shutdown(void) { release_stream_workspaces(); }
 
 }  // extern "C"

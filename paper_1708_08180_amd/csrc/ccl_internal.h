@@ -12,8 +12,10 @@ namespace ccl {
 // True when (tile_h, waves) names a compiled kernel configuration.
 bool config_supported(int th, int nw);
 
-// Enqueue the three phases for one image on `s`.
-hipError_t launch_plain(const ImgView &v, int th, int nw, int conn, hipStream_t s);
+// Enqueue the three phases for one image on `s`.  With ev != nullptr,
+// ev[0..3] are recorded before phase 1, between the phases and after phase 3.
+hipError_t launch_plain(const ImgView &v, int th, int nw, int conn, hipStream_t s,
+                        hipEvent_t *ev = nullptr);
 
 // Workspace layout for one image: masks first (8-byte words), then roots.
 struct WsLayout {

@@ -181,21 +181,25 @@ __global__ void __launch_bounds__(NW * 64) k3_link(ImgView v) {
 // ---------------------------------------------------------------- launchers
 
 template <int TH, int NW, bool CONN8>
-static hipError_t launch_plain_t(const ImgView &v, hipStream_t stream) {
+static hipError_t launch_plain_t(const ImgView &v, hipStream_t stream, hipEvent_t *ev) {
     const uint32_t tiles = (uint32_t)v.tilesX * (uint32_t)v.tilesY;
-    hipLaunchKernelGGL((k1_local_merge<TH, NW, CONN8>), dim3(tiles), dim3(NW * 64), 0, stream, v);
     const uint32_t nH = (uint32_t)v.tilesX * (uint32_t)(v.tilesY - 1);
     const uint32_t nV = (uint32_t)(v.tilesX - 1) * (uint32_t)v.tilesY;
+    if (ev) (void)hipEventRecord(ev[0], stream);
+    hipLaunchKernelGGL((k1_local_merge<TH, NW, CONN8>), dim3(tiles), dim3(NW * 64), 0, stream, v);
+    if (ev) (void)hipEventRecord(ev[1], stream);
     if (nH + nV > 0)
         hipLaunchKernelGGL((k2_boundary<TH, CONN8>), dim3((nH + nV + 3) / 4), dim3(256), 0, stream,
                            v, nH, nV);
+    if (ev) (void)hipEventRecord(ev[2], stream);
     hipLaunchKernelGGL((k3_link<TH, NW, CONN8>), dim3(tiles), dim3(NW * 64), 0, stream, v);
+    if (ev) (void)hipEventRecord(ev[3], stream);
     return hipGetLastError();
 }
 
 template <int TH, int NW>
-static hipError_t launch_plain_c(const ImgView &v, int conn, hipStream_t s) {
-    return conn == 8 ? launch_plain_t<TH, NW, true>(v, s) : launch_plain_t<TH, NW, false>(v, s);
+static hipError_t launch_plain_c(const ImgView &v, int conn, hipStream_t s, hipEvent_t *ev) {
+    return conn == 8 ? launch_plain_t<TH, NW, true>(v, s, ev) : launch_plain_t<TH, NW, false>(v, s, ev);
 }
 
 bool config_supported(int th, int nw) {
@@ -207,9 +211,9 @@ bool config_supported(int th, int nw) {
     }
 }
 
-hipError_t launch_plain(const ImgView &v, int th, int nw, int conn, hipStream_t s) {
+hipError_t launch_plain(const ImgView &v, int th, int nw, int conn, hipStream_t s, hipEvent_t *ev) {
 #define CCL_CASE(T, N) \
-    if (th == T && nw == N) return launch_plain_c<T, N>(v, conn, s);
+    if (th == T && nw == N) return launch_plain_c<T, N>(v, conn, s, ev);
     CCL_CASE(16, 1) CCL_CASE(16, 2) CCL_CASE(16, 4) CCL_CASE(16, 8) CCL_CASE(16, 16)
     CCL_CASE(32, 1) CCL_CASE(32, 2) CCL_CASE(32, 4) CCL_CASE(32, 8) CCL_CASE(32, 16)
     CCL_CASE(64, 1) CCL_CASE(64, 2) CCL_CASE(64, 4) CCL_CASE(64, 8) CCL_CASE(64, 16)
