@@ -143,6 +143,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--config", default=None, help="tile_h,waves (default: library choice)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 64 MiB device-to-device copy (a known-size kernel "
+                         "for scaling HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -167,6 +170,14 @@ def main():
     if args.config:
         th, nw = (int(v) for v in args.config.split(","))
         cfg = binding.Config(th, nw)
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy of %d bytes done" % src.numel())
+        del src, dst
 
     results = []
     for name, img in make_workload(args.workload):

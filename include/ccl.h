@@ -84,8 +84,8 @@ int ccl_version(void);
  *         written as described at the top of this file.
  * stream  hipStream_t (void*), NULL for the null stream.
  *
- * Scratch: a small per-(device, stream) workspace (about 0.26 bytes per
- * pixel for the default 64 x 64 tiles) is allocated on first use and grown
+ * Scratch: a per-(device, stream) workspace (about 1.4 bytes per pixel for
+ * the default tiles) is allocated on first use and grown
  * when a larger image arrives on the same stream (growth synchronizes that
  * stream before freeing the old buffer); ccl_shutdown releases it.  Two
  * concurrent calls on the same stream are ordered by the stream; calls on

@@ -103,13 +103,17 @@ ImgView make_view(const uint8_t *img, int32_t H, int32_t W, int64_t pitch, uint3
     v.img = img;
     v.labels = labels;
     v.masks = (uint64_t *)ws;
-    v.roots = (uint32_t *)((char *)ws + l.mask_bytes);
+    char *base = (char *)ws;
+    v.roots = (uint32_t *)(base + l.mask_bytes);
+    v.rowmask = (uint64_t *)(base + l.mask_bytes + l.root_bytes);
+    v.slots = (uint16_t *)(base + l.mask_bytes + l.root_bytes + l.rowmask_bytes);
     v.pitch = pitch;
     v.H = H;
     v.W = W;
     v.tilesX = (W + kTileW - 1) / kTileW;
     v.tilesY = (H + th - 1) / th;
     v.n = (uint32_t)((uint64_t)H * (uint64_t)W);
+    v.aligned16 = (((uintptr_t)img & 15u) == 0 && (pitch & 15) == 0) ? 1 : 0;
     return v;
 }
 

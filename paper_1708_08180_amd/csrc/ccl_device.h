@@ -2,24 +2,29 @@
 //
 // Tile model.  A tile is 64 pixels wide -- one lane of a 64-wide wavefront
 // per column -- and TH rows tall (TH in {16, 32, 64}).  A workgroup of NW
-// wavefronts owns one tile; wavefront w owns rows [w*RPW, (w+1)*RPW) with
-// RPW = TH / NW.  Inside a tile, a row is a 64-bit foreground mask obtained
-// with one ballot, so the paper's row scan plus row-column unification
-// (Sec. II-A-2) collapses to: every pixel's provisional parent is the first
-// pixel of its horizontal run, found in O(1) from the mask.  Only run starts
-// are union-find nodes.  The local UF (Sec. II-A-3) then merges each run with
-// the runs it touches in the row above through LDS atomicMin, always linking
-// the larger index under the smaller.
+// wavefronts owns one tile at a time; wavefront w owns rows [w*RPW,
+// (w+1)*RPW) with RPW = TH / NW.  A tile row is a 64-bit foreground mask, so
+// the paper's row scan plus row-column unification (Sec. II-A-2) collapses
+// to: every pixel's provisional parent is the first pixel of its horizontal
+// run, found in O(1) from the mask.  Only run starts are union-find nodes.
+// The local UF (Sec. II-A-3) then merges each run with the runs it touches in
+// the row above through LDS atomicMin, always linking the larger index under
+// the smaller.
 //
 // Forest encoding in global memory.  labels[p] holds 1 + parent(p); a root r
 // holds r + 1 and background holds 0.  The final output is therefore itself a
 // fully compressed forest, so the link phase can overwrite entries in place
 // while other tiles still walk the forest.
 //
-// Workspace per tile (written by the local merge, read by the boundary
-// analysis): four 64-bit edge masks (top row, bottom row, left column, right
-// column) and, for every cell on those four edges, the global raster index of
-// its tile-local root.
+// Workspace per tile, written by the local merge:
+//   masks[4]        top-row, bottom-row, left-column, right-column foreground
+//                   masks (boundary analysis)
+//   roots[...]      global raster index of the tile-local root of every cell
+//                   on those four edges (boundary analysis)
+//   rowmask[TH]     the 64-bit foreground mask of every tile row (link)
+//   slots[TH][32]   per row, one 16-bit record per run in left-to-right
+//                   order: the run's tile-local root, with kSlotFlag set when
+//                   that root's component touches a shared tile edge (link)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,8 +35,13 @@ namespace ccl {
 constexpr int kTileW = 64;            // tile width == wavefront width
 constexpr uint32_t kFlag = 0x80000000u;  // "touches a shared tile edge" mark in LDS parents
 constexpr uint32_t kIdx = 0x7FFFFFFFu;
+constexpr uint32_t kNone = 0xFFFFFFFFu;   // "no node"
 
 enum { kMaskTop = 0, kMaskBottom = 1, kMaskLeft = 2, kMaskRight = 3 };
+
+// Per-run record handed from the local merge to the link phase.
+constexpr uint16_t kSlotFlag = 0x8000u;  // the component touches a shared tile edge
+constexpr int kSlotsPerRow = 32;         // a 64-pixel row has at most 32 runs
 
 __host__ __device__ constexpr int roots_per_tile(int th) { return 2 * kTileW + 2 * th; }
 __host__ __device__ constexpr int roots_top(int) { return 0; }
@@ -43,12 +53,15 @@ __host__ __device__ constexpr int roots_right(int th) { return 2 * kTileW + th; 
 struct ImgView {
     const uint8_t *img;
     uint32_t *labels;
-    uint64_t *masks;   // [tiles][4]
-    uint32_t *roots;   // [tiles][roots_per_tile(TH)]
+    uint64_t *masks;    // [tiles][4]
+    uint32_t *roots;    // [tiles][roots_per_tile(TH)]
+    uint64_t *rowmask;  // [tiles][TH]
+    uint16_t *slots;    // [tiles][TH][kSlotsPerRow]
     int64_t pitch;
     int32_t H, W;
     int32_t tilesX, tilesY;
-    uint32_t n;        // H * W (<= 2^32 - 1)
+    uint32_t n;         // H * W (<= 2^32 - 1)
+    int32_t aligned16;  // img and pitch are multiples of 16 bytes
 };
 
 // ------------------------------------------------------------------ helpers
@@ -117,15 +130,17 @@ __device__ __forceinline__ Plan plan_pairs(bool start, bool cL, bool cM, bool cR
 // Every parent is strictly smaller than its child, so `p >= x` both detects
 // a root (p == x) and stops on anything that is not a valid parent; every
 // loop below therefore strictly decreases its index and always terminates.
-__device__ __forceinline__ uint32_t lds_find(uint32_t *par, uint32_t x) {
-    // path halving; stores only ever replace a parent by an ancestor
+
+// Find without writes.  Compression is done by the owner of each node only
+// (see the finish pass of the local merge): a path-halving store by one
+// thread can land after another thread stored the final root into the same
+// node and leave a non-root ancestor there, which breaks every later reader
+// that takes par[n] to be the root.
+__device__ __forceinline__ uint32_t lds_root(const uint32_t *par, uint32_t x) {
     while (true) {
         const uint32_t p = lds_ld(&par[x]);
         if (p >= x) return x;
-        const uint32_t gp = lds_ld(&par[p]);
-        if (gp >= p) return p;
-        lds_st(&par[x], gp);
-        x = gp;
+        x = p;
     }
 }
 
@@ -135,8 +150,8 @@ __device__ __forceinline__ uint32_t lds_find(uint32_t *par, uint32_t x) {
 // retried from there, so no concurrent link is ever lost.
 __device__ __forceinline__ void lds_union(uint32_t *par, uint32_t a, uint32_t b) {
     while (true) {
-        a = lds_find(par, a);
-        b = lds_find(par, b);
+        a = lds_root(par, a);
+        b = lds_root(par, b);
         if (a == b) return;
         if (a > b) { const uint32_t t = a; a = b; b = t; }
         const uint32_t old = atomicMin(&par[b], a);
@@ -173,6 +188,30 @@ __device__ __forceinline__ void g_union(uint32_t *L, uint32_t n, uint32_t a, uin
     }
 }
 
+// Keep, of all (a, b) merge requests a wavefront holds in two slots, only
+// the first occurrence of every distinct pair (lanes with b == kNone hold
+// none).  Along one tile edge most requests repeat the same two tile-local
+// roots, so this cuts the global unions to one per distinct pair.
+__device__ __forceinline__ void dedupe_pairs(uint32_t a, uint32_t b0, uint32_t b1, bool &keep0,
+                                             bool &keep1) {
+    const int lane = (int)(threadIdx.x & 63);
+    uint64_t pend0 = __ballot(b0 != kNone), pend1 = __ballot(b1 != kNone);
+    keep0 = false;
+    keep1 = false;
+    while (pend0 | pend1) {
+        const bool first = pend0 != 0;
+        const int lead = __builtin_ctzll(first ? pend0 : pend1);
+        const uint32_t A = (uint32_t)__builtin_amdgcn_readlane((int)a, lead);
+        const uint32_t B = (uint32_t)__builtin_amdgcn_readlane((int)(first ? b0 : b1), lead);
+        if (lane == lead) {
+            if (first) keep0 = true;
+            else keep1 = true;
+        }
+        pend0 &= ~__ballot(b0 != kNone && a == A && b0 == B);
+        pend1 &= ~__ballot(b1 != kNone && a == A && b1 == B);
+    }
+}
+
 // Find for the link phase.  No link is made any more, so every root is
 // final and every path node may be overwritten with the root (full path
 // compression with plain stores: all writers store the same value).
@@ -191,19 +230,6 @@ __device__ __forceinline__ uint32_t g_find_final(uint32_t *L, uint32_t x) {
 
 // ------------------------------------------------------ tile-local labeling
 
-template <int TH, int NW>
-struct TileLds {
-    uint32_t par[TH * kTileW];   // parents of run starts (local indices)
-    uint64_t msk[TH];            // foreground mask of every tile row
-};
-
-// Per-lane state that the local merge leaves behind for the caller.
-template <int RPW>
-struct TileRegs {
-    uint64_t m[RPW];      // row masks of this wavefront's rows (wave-uniform)
-    uint32_t root[RPW];   // local root (index within the tile) of this lane's pixel
-};
-
 __device__ __forceinline__ uint32_t global_index(const ImgView &v, int tx, int ty, int th,
                                                  uint32_t l) {
     const uint64_t y = (uint64_t)ty * th + (l >> 6);
@@ -211,86 +237,164 @@ __device__ __forceinline__ uint32_t global_index(const ImgView &v, int tx, int t
     return (uint32_t)(y * (uint64_t)v.W + x);
 }
 
-// Phase-1 body shared by the local merge and the link kernel: load the tile,
-// label runs, merge runs across rows in LDS, compress, and mark the roots of
-// components that touch a tile edge shared with another tile.
-// Ends after a workgroup barrier; par[] then holds, for every run start, its
-// root; roots carry kFlag when their component touches a shared edge.
-template <int TH, int NW, bool CONN8>
-__device__ __forceinline__ void tile_local(const ImgView &v, int tx, int ty, TileLds<TH, NW> &sh,
-                                           TileRegs<TH / NW> &rg) {
-    constexpr int RPW = TH / NW;
-    const int lane = lane_id();
-    const int wave = (int)(threadIdx.x >> 6);
-    const int x = tx * kTileW + lane;
-    const int y0 = ty * TH + wave * RPW;
-    const bool xin = x < v.W;
+// Bit i (i < 4) set iff byte i of w is nonzero: fold every byte onto its low
+// bit, then gather the four low bits into bits 28..31 with one multiply (the
+// shifted copies land on distinct bits below 24, so nothing carries).
+__device__ __forceinline__ uint32_t nonzero_bytes4(uint32_t w) {
+    uint32_t t = w | (w >> 4);
+    t |= t >> 2;
+    t |= t >> 1;
+    t &= 0x01010101u;
+    return (t * 0x10204080u) >> 28;
+}
 
-    uint8_t pix[RPW];
-    const uint8_t *src = v.img + (int64_t)y0 * v.pitch + x;
-#pragma unroll
-    for (int k = 0; k < RPW; ++k) pix[k] = (xin && (y0 + k) < v.H) ? src[(int64_t)k * v.pitch] : 0;
+__device__ __forceinline__ uint32_t nonzero_bytes16(uint4 b) {
+    return nonzero_bytes4(b.x) | (nonzero_bytes4(b.y) << 4) | (nonzero_bytes4(b.z) << 8) |
+           (nonzero_bytes4(b.w) << 12);
+}
 
-    uint32_t rs[RPW];  // local index of this lane's run start
+// 16 pixels of one tile row: row `row` of tile (tx, ty), columns
+// [16q, 16q + 16).  One 16-byte load when the chunk is aligned and inside
+// the image, byte loads with zero fill otherwise.
+__device__ __forceinline__ uint4 load_chunk(const ImgView &v, int tx, int ty, int th, int row,
+                                            int q) {
+    const int y = ty * th + row;
+    const int x = tx * kTileW + q * 16;
+    uint4 b = make_uint4(0u, 0u, 0u, 0u);
+    if (y >= v.H) return b;
+    const uint8_t *p = v.img + (int64_t)y * v.pitch + x;
+    if (v.aligned16 && x + 16 <= v.W) return *(const uint4 *)p;
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
+    for (int i = 0; i < 16; ++i)
+        if (x + i < v.W) w[i >> 2] |= (uint32_t)p[i] << (8 * (i & 3));
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// ------------------------------------------------- run-indexed local forest
+//
+// Inside K1 the union-find nodes are runs: run k (0-based, left to right) of
+// tile row r is node r*32 + k.  Run order within a row follows the columns
+// and rows follow each other, so node order is raster order of run starts
+// and the smallest node of a component is the run holding its smallest
+// pixel.  col[node] keeps the run's first column.
+
+// Lane predicate from a wave-uniform 64-bit mask (no VALU work).
+__device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// Number of set bits of m strictly below this lane.
+__device__ __forceinline__ uint32_t bits_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Value of lane-1 / lane+1 (whole-wave DPP shifts; lane 0 / 63 get `edge`).
+__device__ __forceinline__ uint32_t from_left(uint32_t v, uint32_t edge) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t from_right(uint32_t v, uint32_t edge) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x130, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ uint64_t run_starts(uint64_t d) { return d & ~(d << 1); }
+
+// A value every lane holds identically, moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Which (lower run, upper run) pairs of two adjacent rows inside one tile are
+// merged, as lane masks over the lower row d with the upper row u: every pair
+// of runs that touch is taken exactly once, by the leftmost lower cell
+// adjacent to the upper run.  8-connectivity: PL = the upper run containing
+// column j-1 (only at a lower run start), PM = the upper run starting at j
+// (only at a lower run start whose above-left is empty), PR = the upper run
+// starting at j+1.  4-connectivity: PM = the upper run containing j, at the
+// lower run start or where the upper run starts.
+struct PairMasks { uint64_t pl, pm, pr; };
+
+template <bool CONN8>
+__device__ __forceinline__ PairMasks pair_masks(uint64_t d, uint64_t u) {
+    const uint64_t S = run_starts(d);
+    PairMasks p;
+    if (CONN8) {
+        p.pl = S & (u << 1);
+        p.pm = S & u & ~(u << 1);
+        p.pr = d & (u >> 1) & ~u;
+    } else {
+        p.pl = 0;
+        p.pm = d & u & (S | ~(u << 1));
+        p.pr = 0;
+    }
+    return p;
+}
+
+// Sweep of one wavefront's band of rows, top to bottom (Sec. II-A-2/3).
+// `ra` carries, per lane, the root node of the pixel above (kNone for
+// background), so the roots a run touches come from neighbouring lanes'
+// registers.  A run's parent becomes the smallest of those roots (LDS
+// atomicMin on its node); every other root it touches is joined to that one
+// by a real union, which is rare.  Only after a row that had one are the
+// row's roots re-resolved, so `ra` always holds true roots.
+template <int TH, int RPW, bool CONN8>
+__device__ __forceinline__ void sweep_band(uint32_t *par, uint8_t *col, const uint64_t *msk,
+                                           int wave, int lane) {
+    uint32_t ra = kNone;
+    uint64_t u = 0;
     for (int k = 0; k < RPW; ++k) {
         const int r = wave * RPW + k;
-        const uint64_t m = __ballot(pix[k] != 0);
-        rg.m[k] = m;
-        if (lane == 0) lds_st(&sh.msk[r], m);
-        const bool fg = bit(m, lane);
-        const int s = fg ? run_start(m, lane) : lane;
-        rs[k] = (uint32_t)(r * kTileW + s);
-        if (fg && s == lane) lds_st(&sh.par[r * kTileW + lane], (uint32_t)(r * kTileW + lane));
+        const uint64_t d = uniform64(msk[r]);
+        const uint64_t S = run_starts(d);
+        const bool fg = lane_in(d), isS = lane_in(S);
+        const uint32_t node = (uint32_t)(r * kSlotsPerRow) + bits_below(S) - (isS ? 0u : 1u);
+        if (isS) {
+            lds_st(&par[node], node);
+            col[node] = (uint8_t)lane;
+        }
+        uint32_t md = fg ? node : kNone;
+        if (k > 0) {
+            const PairMasks p = pair_masks<CONN8>(d, u);
+            const uint32_t rL = from_left(ra, kNone), rR = from_right(ra, kNone);
+            const uint32_t t0 = lane_in(p.pl) ? rL : (lane_in(p.pm) ? ra : kNone);
+            const uint32_t t1 = lane_in(p.pr) ? rR : kNone;
+            if (t0 != kNone) atomicMin(&par[node], t0);
+            if (t1 != kNone) atomicMin(&par[node], t1);
+            if (fg) md = lds_ld(&par[node]);
+            const bool n0 = t0 != kNone && t0 != md;
+            const bool n1 = t1 != kNone && t1 != md;
+            if (__ballot(n0 || n1)) {
+                if (n0) lds_union(par, t0, md);
+                if (n1) lds_union(par, t1, md);
+                if (fg) md = lds_root(par, md);
+                if (isS) lds_st(&par[node], md);
+            }
+        }
+        ra = md;
+        u = d;
     }
-    __syncthreads();
+}
 
-    // merge each run with the runs it touches in the row above
-#pragma unroll
-    for (int k = 0; k < RPW; ++k) {
-        const int r = wave * RPW + k;
-        if (r == 0) continue;
-        const uint64_t d = rg.m[k];
-        if (!bit(d, lane)) continue;
-        const uint64_t u = (k > 0) ? rg.m[k - 1] : lds_ld(&sh.msk[r - 1]);
-        const bool start = !(lane > 0 && bit(d, lane - 1));
-        const bool cL = lane > 0 && bit(u, lane - 1);
-        const bool cM = bit(u, lane);
-        const bool cR = lane < 63 && bit(u, lane + 1);
-        const Plan p = plan_pairs<CONN8>(start, cL, cM, cR, cL && cM, cM && cR);
-        const uint32_t up = (uint32_t)((r - 1) * kTileW);
-        if (p.l) lds_union(sh.par, rs[k], up + run_start(u, lane - 1));
-        if (p.m) lds_union(sh.par, rs[k], up + run_start(u, lane));
-        if (p.r) lds_union(sh.par, rs[k], up + run_start(u, lane + 1));
+// Band seam of a multi-wavefront tile: the first row of band `wave` against
+// the last row of the band above, with general unions (any forest state).
+template <bool CONN8>
+__device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, int r) {
+    const uint64_t d = uniform64(msk[r]), u = uniform64(msk[r - 1]);
+    const uint64_t S = run_starts(d), Su = run_starts(u);
+    const bool isS = lane_in(S);
+    const uint32_t node = (uint32_t)(r * kSlotsPerRow) + bits_below(S) - (isS ? 0u : 1u);
+    const uint32_t up = (uint32_t)((r - 1) * kSlotsPerRow);
+    const uint32_t bu = bits_below(Su);
+    const PairMasks p = pair_masks<CONN8>(d, u);
+    if (CONN8) {
+        // PL: upper run containing j-1 (rank = starts at or below j-1, minus 1);
+        // PM / PR: upper run starting at j / j+1 (rank = starts below j)
+        if (lane_in(p.pl)) lds_union(par, node, up + bu - 1u);
+        else if (lane_in(p.pm)) lds_union(par, node, up + bu);
+        if (lane_in(p.pr)) lds_union(par, node, up + bu);
+    } else {
+        if (lane_in(p.pm)) lds_union(par, node, up + bu - (lane_in(Su) ? 0u : 1u));
     }
-    __syncthreads();
-
-    // full compression: every run start points at its root
-#pragma unroll
-    for (int k = 0; k < RPW; ++k) {
-        const int r = wave * RPW + k;
-        if (bit(rg.m[k], lane) && rs[k] == (uint32_t)(r * kTileW + lane))
-            lds_st(&sh.par[rs[k]], lds_find(sh.par, rs[k]));
-    }
-    __syncthreads();
-
-    // per-pixel root and edge marks (only edges shared with another tile)
-    const bool hasUp = ty > 0, hasDown = ty + 1 < v.tilesY;
-    const bool hasLeft = tx > 0, hasRight = tx + 1 < v.tilesX;
-#pragma unroll
-    for (int k = 0; k < RPW; ++k) {
-        const int r = wave * RPW + k;
-        const bool fg = bit(rg.m[k], lane);
-        const uint32_t root = fg ? (lds_ld(&sh.par[rs[k]]) & kIdx) : 0u;
-        rg.root[k] = root;
-        if (!fg) continue;
-        const bool isStart = rs[k] == (uint32_t)(r * kTileW + lane);
-        const bool mark = ((r == 0 && hasUp) || (r == TH - 1 && hasDown)) ? isStart
-                          : false;
-        const bool markCol = (lane == 0 && hasLeft) || (lane == 63 && hasRight);
-        if (mark || markCol) atomicOr(&sh.par[root], kFlag);
-    }
-    __syncthreads();
 }
 
 }  // namespace ccl

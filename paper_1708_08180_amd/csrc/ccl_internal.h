@@ -17,11 +17,13 @@ bool config_supported(int th, int nw);
 hipError_t launch_plain(const ImgView &v, int th, int nw, int conn, hipStream_t s,
                         hipEvent_t *ev = nullptr);
 
-// Workspace layout for one image: masks first (8-byte words), then roots.
+// Workspace layout for one image: edge masks, edge-cell roots, row masks, run slots.
 struct WsLayout {
     size_t tiles;
     size_t mask_bytes;
     size_t root_bytes;
+    size_t rowmask_bytes;
+    size_t slot_bytes;
     size_t total;
 };
 
@@ -34,7 +36,9 @@ inline WsLayout ws_layout(int H, int W, int th) {
     l.tiles = tx * ty;
     l.mask_bytes = align_up(l.tiles * 4 * sizeof(uint64_t), 256);
     l.root_bytes = align_up(l.tiles * (size_t)roots_per_tile(th) * sizeof(uint32_t), 256);
-    l.total = l.mask_bytes + l.root_bytes;
+    l.rowmask_bytes = align_up(l.tiles * (size_t)th * sizeof(uint64_t), 256);
+    l.slot_bytes = align_up(l.tiles * (size_t)th * kSlotsPerRow * sizeof(uint16_t), 256);
+    l.total = l.mask_bytes + l.root_bytes + l.rowmask_bytes + l.slot_bytes;
     return l;
 }
 

@@ -134,3 +134,16 @@ def test_plain_entry_point():
     img = wl.bernoulli(777, 1234, 0.5, 77)
     for conn in (4, 8):
         _cmp(img, conn, plain=True, what="plain")
+
+
+@pytest.mark.parametrize("config", CONFIGS + [(16, 8), (32, 16), (64, 2)])
+def test_repeated_runs_are_exact(config):
+    # races in concurrent unions show up as run-to-run differences; every
+    # configuration must give the oracle's labels on every repetition
+    imgs = [wl.bernoulli(300, 260, 0.6, 7, g=3), wl.bernoulli(512, 512, 0.5, 3)]
+    for conn in (4, 8):
+        for img in imgs:
+            want = oracle.label(img, conn)
+            for rep in range(8):
+                got = gpu_label(img, conn, config=config)
+                assert np.array_equal(got, want), "config %s conn %d rep %d" % (config, conn, rep)
