@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(NW * 64) k3_link(ImgView v) {
 
 // Resident workgroups of a persistent kernel on the current device
 // (occupancy x compute units), cached per (device, kernel).
-static uint32_t resident_groups(const void *kernel, int threads) {
+[[maybe_unused]] static uint32_t resident_groups(const void *kernel, int threads) {
     static std::mutex mu;
     static std::map<std::pair<int, const void *>, uint32_t> cache;
     int dev = 0;
@@ -313,8 +313,11 @@ static hipError_t launch_plain_t(const ImgView &v, hipStream_t stream, hipEvent_
     const uint32_t tiles = (uint32_t)v.tilesX * (uint32_t)v.tilesY;
     const uint32_t nH = (uint32_t)v.tilesX * (uint32_t)(v.tilesY - 1);
     const uint32_t nV = (uint32_t)(v.tilesX - 1) * (uint32_t)v.tilesY;
-    const uint32_t g1 = resident_groups((const void *)k1_local_merge<TH, NW, CONN8>, NW * 64);
-    const uint32_t grid1 = tiles < g1 ? tiles : g1;
+    // One workgroup per tile: with about as many tiles as resident slots, a
+    // persistent grid leaves a second round of tiles on a few workgroups
+    // while the rest of the chip idles.  The loop in the kernel only runs
+    // more than once for grids capped below the tile count.
+    const uint32_t grid1 = tiles;
     if (ev) (void)hipEventRecord(ev[0], stream);
     hipLaunchKernelGGL((k1_local_merge<TH, NW, CONN8>), dim3(grid1), dim3(NW * 64), 0, stream, v,
                        tiles);

@@ -7,8 +7,8 @@ void default_config(int H, int W, int conn, int *th, int *nw) {
     (void)H;
     (void)W;
     (void)conn;
-    *th = 64;
-    *nw = 4;
+    *th = 32;
+    *nw = 2;
 }
 
 }  // namespace ccl
