@@ -18,6 +18,11 @@
  * for background.  Raster indices use the width W, never the row pitch.
  * The labeling is unique, so results are bit-exact and deterministic.
  *
+ * Linking: libccl.so does not link a HIP runtime itself; it binds to the
+ * libamdhip64 the host process provides (link the program with -lamdhip64,
+ * or load the runtime with RTLD_GLOBAL before loading libccl.so).  Device
+ * pointers and streams passed in must come from that same runtime.
+ *
  * Conventions
  *   - Pointers named img/labels/workspace are DEVICE pointers (hipMalloc or
  *     equivalent) unless stated; descriptor arrays are HOST pointers.
@@ -127,6 +132,93 @@ int ccl_label_2d_ex(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
 int ccl_label_2d_timed(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
                        int32_t connectivity, uint32_t *labels, const ccl_config *cfg,
                        void *stream, float *phase_ms);
+
+/* ------------------------------------------------------------------ batch
+ *
+ * A context labels many images of different sizes in one call (the batched
+ * form): persistent kernels run each phase over the tiles of all images, the
+ * local merge pulling tiles from a device work queue, and the three launches
+ * are replayed from a captured hipGraph.  Results are bit-identical to
+ * ccl_label_2d on each image.
+ */
+typedef struct ccl_ctx ccl_ctx;
+
+/* One image of a batch.  img and labels are device pointers with the same
+ * meaning and layout as in ccl_label_2d. */
+typedef struct ccl_image_desc {
+    const uint8_t *img;
+    uint32_t *labels;
+    int32_t H, W;
+    int64_t pitch;
+} ccl_image_desc;
+
+/* Fixed capacity of a context.
+ * max_images  most images per call (>= 1).
+ * max_pixels  most pixels per call, summed over images (>= 1); the tile
+ *             workspace is sized for it with room for partial tiles.
+ * cfg         tile configuration for every call ({0,0} = the library's
+ *             choice for an image of max_pixels / max_images pixels).
+ * use_graph   nonzero: record the three launches once per connectivity into
+ *             a hipGraph and replay it (needs a non-null stream). */
+typedef struct ccl_ctx_opts {
+    int32_t max_images;
+    int64_t max_pixels;
+    ccl_config cfg;
+    int32_t use_graph;
+} ccl_ctx_opts;
+
+/* Create a context on the current device; allocates its device buffers and
+ * a pinned staging area once.  *out receives the handle. */
+int ccl_ctx_create(ccl_ctx **out, const ccl_ctx_opts *opts);
+
+/* Synchronize the context's last staging copy and free everything it owns.
+ * The caller must have synchronized the streams it labeled on. */
+int ccl_ctx_destroy(ccl_ctx *ctx);
+
+/*
+ * ccl_label_batch -- label n images in one call (same output contract as
+ * ccl_label_2d for every image).
+ * descs  HOST array of n descriptors; copied into the context (the call
+ *        returns before the GPU work finishes; the array may be reused
+ *        immediately).
+ * n      1 <= n <= max_images; 0 is a no-op.
+ * Errors: CCL_ERR_INVALID_ARG for a bad descriptor (index not reported),
+ * CCL_ERR_UNSUPPORTED for connectivity, CCL_ERR_CAPACITY when n or the
+ * total tile count exceeds the context.  One context must not be used by
+ * two host threads at once, and its calls must be ordered on the device:
+ * the kernels of a call read the context's device buffers until they
+ * finish and the next call overwrites them, so use one stream per context
+ * (or order the streams yourself).  The staging area is reused only after
+ * the previous call's copy has completed.
+ */
+int ccl_label_batch(ccl_ctx *ctx, const ccl_image_desc *descs, int32_t n, int32_t connectivity,
+                    void *stream);
+
+/* ---------------------------------------------------------------- tuning
+ *
+ * The tile configuration of ccl_label_2d is taken from a process-wide table
+ * keyed by (size class = floor(log2(H*W)), connectivity); entries come from
+ * ccl_autotune or ccl_tuning_load, misses use the built-in default. */
+
+/* Time every supported tile configuration on the given image (device
+ * buffers as in ccl_label_2d; `labels` is overwritten), `reps` calls each,
+ * and record the fastest for the image's size class and connectivity.
+ * Writes the winner to *best and its mean milliseconds per call to
+ * *best_ms (either may be NULL).  Blocks. */
+int ccl_autotune(const uint8_t *img, int32_t H, int32_t W, int64_t pitch, int32_t connectivity,
+                 uint32_t *labels, int32_t reps, void *stream, ccl_config *best, float *best_ms);
+
+/* Look up the configuration ccl_label_2d would use for H x W. */
+int ccl_tuning_get(int32_t H, int32_t W, int32_t connectivity, ccl_config *out);
+
+/* Save / load the tuning table as JSON lines
+ * {"class": c, "conn": k, "tile_h": t, "waves": w, "ms": m}.
+ * Loading merges into the table; CCL_ERR_INVALID_ARG on a bad file. */
+int ccl_tuning_save(const char *path);
+int ccl_tuning_load(const char *path);
+
+/* Drop every table entry (defaults apply again). */
+void ccl_tuning_clear(void);
 
 /* Release every workspace the library allocated (all devices) after
  * synchronizing the devices that own them.  Later calls allocate again. */

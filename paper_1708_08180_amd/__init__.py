@@ -7,9 +7,16 @@ library is loaded on first use; a missing or unbuilt library raises
 ``RuntimeError`` -- there is no CPU fallback.
 """
 from .binding import (  # noqa: F401
+    BatchContext,
     CclError,
+    autotune,
     label,
     label_batch,
+    label_plain,
     library_path,
     load_library,
+    tuning_clear,
+    tuning_get,
+    tuning_load,
+    tuning_save,
 )

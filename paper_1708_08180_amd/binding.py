@@ -34,9 +34,8 @@ class ImageDesc(ctypes.Structure):
 
 
 class CtxOpts(ctypes.Structure):
-    _fields_ = [("max_images", ctypes.c_int32), ("max_tiles", ctypes.c_int64),
-                ("tile_h", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+    _fields_ = [("max_images", ctypes.c_int32), ("max_pixels", ctypes.c_int64),
+                ("cfg", Config), ("use_graph", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -56,11 +55,51 @@ SIGNATURES = {
     "ccl_label_2d_timed": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, ctypes.POINTER(Config), _P,
                                           ctypes.POINTER(ctypes.c_float)]),
     "ccl_shutdown": (None, []),
+    "ccl_ctx_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(CtxOpts)]),
+    "ccl_ctx_destroy": (ctypes.c_int, [_P]),
+    "ccl_label_batch": (ctypes.c_int, [_P, ctypes.POINTER(ImageDesc), _I32, _I32, _P]),
+    "ccl_autotune": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, _I32, _P, ctypes.POINTER(Config),
+                                    ctypes.POINTER(ctypes.c_float)]),
+    "ccl_tuning_get": (ctypes.c_int, [_I32, _I32, _I32, ctypes.POINTER(Config)]),
+    "ccl_tuning_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "ccl_tuning_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "ccl_tuning_clear": (None, []),
 }
 
 
 def library_path() -> str:
     return _LIB_PATH
+
+
+_hip_rt = None
+
+
+def _load_hip_runtime():
+    """Make a HIP runtime's symbols global before libccl.so is loaded.
+
+    libccl.so does not link a HIP runtime of its own.  When torch is present
+    its bundled runtime is the one that owns the tensors and streams handed to
+    the library, so that one is used; otherwise the ROCm installation's."""
+    global _hip_rt
+    if _hip_rt is not None:
+        return _hip_rt
+    candidates = []
+    try:
+        import torch
+
+        candidates.append(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so"))
+    except ImportError:
+        pass
+    candidates += ["libamdhip64.so", "/opt/rocm/lib/libamdhip64.so"]
+    for c in candidates:
+        if os.path.sep in c and not os.path.exists(c):
+            continue
+        try:
+            _hip_rt = ctypes.CDLL(c, mode=ctypes.RTLD_GLOBAL)
+            return _hip_rt
+        except OSError:
+            continue
+    raise CclError("no HIP runtime (libamdhip64.so) could be loaded")
 
 
 def load_library():
@@ -74,6 +113,7 @@ def load_library():
         if not os.path.exists(_LIB_PATH):
             raise CclError("libccl.so is not built (expected at %s); run __graft_entry__.build()"
                            % _LIB_PATH)
+        _load_hip_runtime()
         lib = ctypes.CDLL(_LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)
@@ -193,5 +233,98 @@ def shutdown():
     load_library().ccl_shutdown()
 
 
-def label_batch(*args, **kwargs):
-    raise CclError("label_batch is not available in this build")
+class BatchContext:
+    """Owns a ccl_ctx (fixed capacity, device buffers, captured graphs)."""
+
+    def __init__(self, max_images: int, max_pixels: int, config=None, use_graph: bool = True):
+        lib = load_library()
+        opts = CtxOpts(int(max_images), int(max_pixels),
+                       Config(*(config if config else (0, 0))), 1 if use_graph else 0)
+        h = ctypes.c_void_p()
+        _check(lib.ccl_ctx_create(ctypes.byref(h), ctypes.byref(opts)), "ccl_ctx_create")
+        self._h = h
+        self.max_images = int(max_images)
+        self.max_pixels = int(max_pixels)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _check(load_library().ccl_ctx_destroy(self._h), "ccl_ctx_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def descs(self, images, outs):
+        arr = (ImageDesc * len(images))()
+        for k, (img, out) in enumerate(zip(images, outs)):
+            _check_image(img)
+            H, W = img.shape
+            if out.shape != (H, W) or out.dtype != _torch().int32 or not out.is_contiguous():
+                raise ValueError("out[%d] must be a contiguous int32 tensor of shape (H, W)" % k)
+            arr[k] = ImageDesc(img.data_ptr(), out.data_ptr(), H, W, _pitch(img))
+        return arr
+
+    def label(self, images, conn: int = 8, outs=None, stream=None, descs=None):
+        """Label a list of 2D uint8 device images in one call; returns the list
+        of int32 label tensors (uint32 bits).  `descs` may be a prebuilt
+        descriptor array from ``descs()`` for the same tensors."""
+        torch = _torch()
+        if outs is None:
+            outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in images]
+        if descs is None:
+            descs = self.descs(images, outs)
+        rc = load_library().ccl_label_batch(self._h, descs, len(images), int(conn),
+                                             _stream_handle(stream))
+        _check(rc, "ccl_label_batch")
+        return outs
+
+
+def label_batch(images, conn: int = 8, ctx: BatchContext = None, stream=None):
+    """Label several images with one batched call (a context is created when
+    none is given)."""
+    if ctx is None:
+        px = sum(int(im.shape[0]) * int(im.shape[1]) for im in images)
+        ctx = BatchContext(max(1, len(images)), max(1, px))
+    return ctx.label(images, conn, stream=stream)
+
+
+def autotune(img, conn: int = 8, reps: int = 5, stream=None):
+    """Time every tile configuration on `img`, record the fastest for its size
+    class; returns ((tile_h, waves), ms_per_call)."""
+    torch = _torch()
+    _check_image(img)
+    H, W = img.shape
+    out = torch.empty((H, W), dtype=torch.int32, device=img.device)
+    best = Config(0, 0)
+    ms = ctypes.c_float(0.0)
+    lib = load_library()
+    with torch.cuda.device(img.device):
+        rc = lib.ccl_autotune(img.data_ptr(), H, W, _pitch(img), int(conn), out.data_ptr(), int(reps),
+                              _stream_handle(stream), ctypes.byref(best), ctypes.byref(ms))
+    _check(rc, "ccl_autotune")
+    return (best.tile_h, best.waves), float(ms.value)
+
+
+def tuning_get(H: int, W: int, conn: int = 8):
+    c = Config(0, 0)
+    _check(load_library().ccl_tuning_get(int(H), int(W), int(conn), ctypes.byref(c)), "ccl_tuning_get")
+    return (c.tile_h, c.waves)
+
+
+def tuning_save(path: str):
+    _check(load_library().ccl_tuning_save(os.fsencode(path)), "ccl_tuning_save")
+
+
+def tuning_load(path: str):
+    _check(load_library().ccl_tuning_load(os.fsencode(path)), "ccl_tuning_load")
+
+
+def tuning_clear():
+    load_library().ccl_tuning_clear()

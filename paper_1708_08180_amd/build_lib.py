@@ -18,9 +18,12 @@ LIB = os.path.join(PKG, "libccl.so")
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-# Packed FP32 instructions are disabled for all device code.
+# Packed FP32 instructions are disabled for all device code.  Code object v5
+# loads under every HIP runtime this library may meet (the ROCm install or the
+# runtime bundled with a framework such as torch).
 HIP_FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-fno-strict-aliasing",
+    "-mcode-object-version=5",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + INCLUDE, "-I" + CSRC,
 ]
@@ -49,7 +52,10 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    # No HIP runtime is linked in: the library binds to the runtime the host
+    # process already has, so device pointers and streams it is handed come
+    # from the same runtime that launches its kernels.
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-no-hip-rt", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))

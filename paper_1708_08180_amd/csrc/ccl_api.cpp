@@ -18,10 +18,6 @@ int fail_hip(hipError_t e) {
     return CCL_ERR_HIP;
 }
 
-// Default tile configuration.  The tuning table (ccl_tune.cpp) may override
-// it per size class and connectivity.
-void default_config(int H, int W, int conn, int *th, int *nw);
-
 namespace {
 
 struct WsEntry {

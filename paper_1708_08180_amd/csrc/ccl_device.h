@@ -64,6 +64,34 @@ struct ImgView {
     int32_t aligned16;  // img and pitch are multiples of 16 bytes
 };
 
+// One image of a batch as the batch kernels see it (device descriptor).
+// Tiles of all images are numbered consecutively: image i owns global tiles
+// [tile_base, tile_base + tilesX*tilesY) and edge segments
+// [seg_base, seg_base + nH + nV); its workspace lives at those tile offsets.
+struct BatchImage {
+    const uint8_t *img;
+    uint32_t *labels;
+    int64_t pitch;
+    int32_t H, W;
+    int32_t tilesX, tilesY;
+    uint32_t n;
+    int32_t aligned16;
+    uint32_t tile_base, seg_base;
+    uint32_t nH, nV;
+};
+
+struct BatchHeader {
+    uint32_t n_images, total_tiles, total_segs, pad;
+};
+
+// Workspace of a batch context, indexed by global tile.
+struct BatchWs {
+    uint64_t *masks;
+    uint32_t *roots;
+    uint64_t *rowmask;
+    uint16_t *slots;
+};
+
 // ------------------------------------------------------------------ helpers
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }

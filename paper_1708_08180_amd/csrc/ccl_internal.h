@@ -5,12 +5,19 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "ccl.h"
 #include "ccl_device.h"
 
 namespace ccl {
 
 // True when (tile_h, waves) names a compiled kernel configuration.
 bool config_supported(int th, int nw);
+
+// Enqueue the three batch phases (persistent kernels) on `s`.  hdr and
+// descs are device pointers; queue is a zeroed device counter that the
+// boundary kernel re-zeroes for the next call.
+hipError_t launch_batch(const BatchHeader *hdr, const BatchImage *descs, const BatchWs &w,
+                        uint32_t *queue, int th, int nw, int conn, hipStream_t s);
 
 // Enqueue the three phases for one image on `s`.  With ev != nullptr,
 // ev[0..3] are recorded before phase 1, between the phases and after phase 3.
@@ -41,5 +48,11 @@ inline WsLayout ws_layout(int H, int W, int th) {
     l.total = l.mask_bytes + l.root_bytes + l.rowmask_bytes + l.slot_bytes;
     return l;
 }
+
+// Shared by the entry points.
+int fail_hip(hipError_t e);
+int validate_image(const void *img, int32_t H, int32_t W, int64_t pitch, const void *labels);
+int resolve_config(int H, int W, int conn, const ccl_config *cfg, int *th, int *nw);
+void default_config(int H, int W, int conn, int *th, int *nw);
 
 }  // namespace ccl

@@ -1,16 +1,23 @@
-// The three labeling kernels for one image (gfx950) and their launchers.
+// The three labeling kernels (gfx950) for one image and for a batch, and
+// their launchers.
 //
-//   k1_local_merge     Sec. II-A (Kernel 1): tile-local merge with coarse
+//   local merge        Sec. II-A (Kernel 1): tile-local merge with coarse
 //                      labeling; writes the tile's edge masks and edge-cell
-//                      roots to the workspace and seeds labels[root] = root+1
-//                      for roots whose component touches a shared tile edge.
-//   k2_boundary        Sec. II-B (Kernel 2): union-find on tile-edge cells
-//                      only, one wavefront per tile edge; the only kernel
-//                      with global atomics.
-//   k3_link            Sec. II-C: reads each pixel's tile-local root from the
-//                      workspace, resolves each edge-touching local root once
+//                      roots, its row masks and per-run records to the
+//                      workspace, and seeds labels[root] = root + 1 for roots
+//                      whose component touches a shared tile edge.
+//   boundary analysis  Sec. II-B (Kernel 2): union-find on tile-edge cells
+//                      only, one wavefront per tile edge; the only phase with
+//                      global atomics.
+//   link               Sec. II-C: reads each tile's row masks and run
+//                      records, resolves each edge-touching local root once
 //                      in the global forest and writes the dense output
 //                      labels (1 + root, 0 for background).
+//
+// The per-tile and per-edge bodies are device functions shared by the
+// single-image kernels (one workgroup per tile / per four edges) and the
+// batch kernels (persistent workgroups over the tiles of all images; the
+// local merge pulls tiles from a device work queue).
 #include <map>
 #include <mutex>
 #include <utility>
@@ -31,144 +38,133 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nb) {
     return xcd * q + (xcd < r ? xcd : r) + i;
 }
 
-// Local merge (Kernel 1).  Persistent: each workgroup walks tiles
-// worker, worker + G, ... and issues the loads of its next tile before it
-// starts merging the current one, so the image streams in while the LDS
-// union-find runs.
+// ------------------------------------------------------------- local merge
+
+template <int TH>
+struct K1Lds {
+    uint32_t par[TH * kSlotsPerRow];  // run-indexed parents
+    uint8_t col[TH * kSlotsPerRow];   // first column of every run
+    uint64_t msk[TH];                 // row masks
+};
+
+// Kernel 1 body for tile t of image v.  Ends after a workgroup barrier, so
+// the caller may reuse the LDS for the next tile.
 template <int TH, int NW, bool CONN8>
-__global__ void __launch_bounds__(NW * 64) k1_local_merge(ImgView v, uint32_t ntiles) {
+__device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH> &sh) {
     constexpr int RPW = TH / NW;
     constexpr int NT = NW * 64;
     constexpr int CH = TH * 4;                  // 16-byte chunks per tile
     constexpr int LPT = (CH + NT - 1) / NT;     // chunks per thread
     constexpr int NODES = TH * kSlotsPerRow;    // run-indexed nodes per tile
     constexpr int NPT = (NODES + NT - 1) / NT;  // nodes per thread
-    __shared__ uint32_t par[NODES];
-    __shared__ uint8_t col[NODES];
-    __shared__ uint64_t msk[TH];
+    uint32_t *par = sh.par;
+    uint8_t *col = sh.col;
+    uint64_t *msk = sh.msk;
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t G = gridDim.x;
-    uint32_t t = xcd_remap(blockIdx.x, G);
     const uint32_t TX = (uint32_t)v.tilesX;
+    const int tx = (int)(t % TX), ty = (int)(t / TX);
 
-    uint4 buf[LPT];
-    if (t < ntiles) {
+    // row masks into LDS (16 pixels per chunk)
 #pragma unroll
-        for (int i = 0; i < LPT; ++i) {
-            const int c = tid + i * NT;
-            if (c < CH) buf[i] = load_chunk(v, (int)(t % TX), (int)(t / TX), TH, c >> 2, c & 3);
+    for (int i = 0; i < LPT; ++i) {
+        const int c = tid + i * NT;
+        if (c < CH)
+            ((uint16_t *)msk)[c] = (uint16_t)nonzero_bytes16(load_chunk(v, tx, ty, TH, c >> 2, c & 3));
+    }
+    __syncthreads();
+    sweep_band<TH, RPW, CONN8>(par, col, msk, wave, lane);
+    if (NW > 1) {
+        __syncthreads();
+        if (wave > 0) merge_seam<CONN8>(par, msk, wave * RPW);
+    }
+    __syncthreads();
+
+    // node-parallel finish: compress (each node written by its owner only, so
+    // par[n] is the root afterwards), mark edge-touching roots, emit records
+    const bool hasUp = ty > 0, hasDown = ty + 1 < v.tilesY;
+    const bool hasLeft = tx > 0, hasRight = tx + 1 < v.tilesX;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int n = tid + i * NT;
+        if (n >= NODES) break;
+        const uint64_t d = msk[n >> 5];
+        if ((n & 31) < __popcll(run_starts(d))) lds_st(&par[n], lds_root(par, (uint32_t)n));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int n = tid + i * NT;
+        if (n >= NODES) break;
+        const int r = n >> 5, k = n & 31;
+        const uint64_t d = msk[r];
+        const int runs = __popcll(run_starts(d));
+        if (k >= runs) continue;
+        const bool edge = (r == 0 && hasUp) || (r == TH - 1 && hasDown) ||
+                          (k == 0 && (d & 1ull) && hasLeft) ||
+                          (k == runs - 1 && (d >> 63) && hasRight);
+        if (edge) atomicOr(&par[lds_ld(&par[n]) & kIdx], kFlag);
+    }
+    __syncthreads();
+    uint16_t *sl = v.slots + (size_t)t * TH * kSlotsPerRow;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int n = tid + i * NT;
+        if (n >= NODES) break;
+        const uint64_t d = msk[n >> 5];
+        if ((n & 31) >= __popcll(run_starts(d))) continue;
+        const uint32_t root = lds_ld(&par[n]) & kIdx;
+        const uint32_t flag = lds_ld(&par[root]) & kFlag;
+        const uint32_t rpix = (root >> 5) * kTileW + col[root];
+        sl[n] = (uint16_t)(rpix | (flag ? kSlotFlag : 0u));
+        if (root == (uint32_t)n && flag) {
+            const uint32_t g = global_index(v, tx, ty, TH, rpix);
+            v.labels[g] = g + 1u;
         }
     }
-    for (; t < ntiles; t += G) {
-        const int tx = (int)(t % TX), ty = (int)(t / TX);
-        // row masks into LDS (16 pixels per chunk)
-#pragma unroll
-        for (int i = 0; i < LPT; ++i) {
-            const int c = tid + i * NT;
-            if (c < CH) ((uint16_t *)msk)[c] = (uint16_t)nonzero_bytes16(buf[i]);
-        }
-        __syncthreads();
-        // prefetch the next tile while this one is merged
-        const uint32_t tn = t + G;
-        if (tn < ntiles) {
-#pragma unroll
-            for (int i = 0; i < LPT; ++i) {
-                const int c = tid + i * NT;
-                if (c < CH) buf[i] = load_chunk(v, (int)(tn % TX), (int)(tn / TX), TH, c >> 2, c & 3);
-            }
-        }
-        sweep_band<TH, RPW, CONN8>(par, col, msk, wave, lane);
-        if (NW > 1) {
-            __syncthreads();
-            if (wave > 0) merge_seam<CONN8>(par, msk, wave * RPW);
-        }
-        __syncthreads();
-
-        // node-parallel finish: compress (each node written by its owner only, so
-        // par[n] is the root afterwards), mark edge-touching roots, emit records
-        const bool hasUp = ty > 0, hasDown = ty + 1 < v.tilesY;
-        const bool hasLeft = tx > 0, hasRight = tx + 1 < v.tilesX;
-#pragma unroll
-        for (int i = 0; i < NPT; ++i) {
-            const int n = tid + i * NT;
-            if (n >= NODES) break;
-            const uint64_t d = msk[n >> 5];
-            if ((n & 31) < __popcll(run_starts(d))) lds_st(&par[n], lds_root(par, (uint32_t)n));
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NPT; ++i) {
-            const int n = tid + i * NT;
-            if (n >= NODES) break;
-            const int r = n >> 5, k = n & 31;
-            const uint64_t d = msk[r];
-            const int runs = __popcll(run_starts(d));
-            if (k >= runs) continue;
-            const bool edge = (r == 0 && hasUp) || (r == TH - 1 && hasDown) ||
-                              (k == 0 && (d & 1ull) && hasLeft) ||
-                              (k == runs - 1 && (d >> 63) && hasRight);
-            if (edge) atomicOr(&par[lds_ld(&par[n]) & kIdx], kFlag);
-        }
-        __syncthreads();
-        uint16_t *sl = v.slots + (size_t)t * TH * kSlotsPerRow;
-#pragma unroll
-        for (int i = 0; i < NPT; ++i) {
-            const int n = tid + i * NT;
-            if (n >= NODES) break;
-            const uint64_t d = msk[n >> 5];
-            if ((n & 31) >= __popcll(run_starts(d))) continue;
+    if (tid < TH) v.rowmask[(size_t)t * TH + tid] = msk[tid];
+    // edge masks and edge-cell roots for the boundary analysis
+    if (wave == 0) {
+        uint64_t *mk = v.masks + (size_t)t * 4;
+        uint32_t *rt = v.roots + (size_t)t * roots_per_tile(TH);
+        const uint64_t mTop = uniform64(msk[0]);
+        const uint64_t mBot = uniform64(msk[TH - 1]);
+        // root pixel (tile-local index) of run node n
+        auto root_pix = [&](uint32_t n) {
             const uint32_t root = lds_ld(&par[n]) & kIdx;
-            const uint32_t flag = lds_ld(&par[root]) & kFlag;
-            const uint32_t rpix = (root >> 5) * kTileW + col[root];
-            sl[n] = (uint16_t)(rpix | (flag ? kSlotFlag : 0u));
-            if (root == (uint32_t)n && flag) {
-                const uint32_t g = global_index(v, tx, ty, TH, rpix);
-                v.labels[g] = g + 1u;
-            }
+            return (root >> 5) * kTileW + col[root];
+        };
+        if (hasUp && lane_in(mTop)) {
+            const uint64_t S = run_starts(mTop);
+            const uint32_t n = bits_below(S) - (lane_in(S) ? 0u : 1u);
+            rt[roots_top(TH) + lane] = global_index(v, tx, ty, TH, root_pix(n));
         }
-        if (tid < TH) v.rowmask[(size_t)t * TH + tid] = msk[tid];
-        // edge masks and edge-cell roots for the boundary analysis
-        if (wave == 0) {
-            uint64_t *mk = v.masks + (size_t)t * 4;
-            uint32_t *rt = v.roots + (size_t)t * roots_per_tile(TH);
-            const uint64_t mTop = uniform64(msk[0]);
-            const uint64_t mBot = uniform64(msk[TH - 1]);
-            // root pixel (tile-local index) of run node n
-            auto root_pix = [&](uint32_t n) {
-                const uint32_t root = lds_ld(&par[n]) & kIdx;
-                return (root >> 5) * kTileW + col[root];
-            };
-            if (hasUp && lane_in(mTop)) {
-                const uint64_t S = run_starts(mTop);
-                const uint32_t n = bits_below(S) - (lane_in(S) ? 0u : 1u);
-                rt[roots_top(TH) + lane] = global_index(v, tx, ty, TH, root_pix(n));
-            }
-            if (hasDown && lane_in(mBot)) {
-                const uint64_t S = run_starts(mBot);
-                const uint32_t n = (uint32_t)((TH - 1) * kSlotsPerRow) + bits_below(S) -
-                                   (lane_in(S) ? 0u : 1u);
-                rt[roots_bottom(TH) + lane] = global_index(v, tx, ty, TH, root_pix(n));
-            }
-            const uint64_t mr = lane < TH ? msk[lane] : 0ull;
-            const bool lb = (mr & 1ull) != 0, rb = (mr >> 63) != 0;
-            const uint64_t mLeft = __ballot(lb), mRight = __ballot(rb);
-            if (hasLeft && lb)
-                rt[roots_left(TH) + lane] =
-                    global_index(v, tx, ty, TH, root_pix((uint32_t)(lane * kSlotsPerRow)));
-            if (hasRight && rb)
-                rt[roots_right(TH) + lane] = global_index(
-                    v, tx, ty, TH,
-                    root_pix((uint32_t)(lane * kSlotsPerRow + __popcll(run_starts(mr)) - 1)));
-            if (lane == 0) {
-                mk[kMaskTop] = mTop;
-                mk[kMaskBottom] = mBot;
-                mk[kMaskLeft] = mLeft;
-                mk[kMaskRight] = mRight;
-            }
+        if (hasDown && lane_in(mBot)) {
+            const uint64_t S = run_starts(mBot);
+            const uint32_t n = (uint32_t)((TH - 1) * kSlotsPerRow) + bits_below(S) -
+                               (lane_in(S) ? 0u : 1u);
+            rt[roots_bottom(TH) + lane] = global_index(v, tx, ty, TH, root_pix(n));
         }
-        __syncthreads();  // LDS is reused by the next tile
+        const uint64_t mr = lane < TH ? msk[lane] : 0ull;
+        const bool lb = (mr & 1ull) != 0, rb = (mr >> 63) != 0;
+        const uint64_t mLeft = __ballot(lb), mRight = __ballot(rb);
+        if (hasLeft && lb)
+            rt[roots_left(TH) + lane] =
+                global_index(v, tx, ty, TH, root_pix((uint32_t)(lane * kSlotsPerRow)));
+        if (hasRight && rb)
+            rt[roots_right(TH) + lane] = global_index(
+                v, tx, ty, TH,
+                root_pix((uint32_t)(lane * kSlotsPerRow + __popcll(run_starts(mr)) - 1)));
+        if (lane == 0) {
+            mk[kMaskTop] = mTop;
+            mk[kMaskBottom] = mBot;
+            mk[kMaskLeft] = mLeft;
+            mk[kMaskRight] = mRight;
+        }
     }
+    __syncthreads();  // LDS may be reused for another tile
 }
+
+// ------------------------------------------------------ boundary analysis
 
 // One wavefront per tile edge.  Edge segments [0, nH) are the horizontal
 // edges (tile (tx, ty) against the tile above, ty >= 1), segments
@@ -177,10 +173,8 @@ __global__ void __launch_bounds__(NW * 64) k1_local_merge(ImgView v, uint32_t nt
 // a tile corner; vertical edges take only pairs inside one tile row, so every
 // adjacent foreground pair that crosses tiles is examined by exactly one edge.
 template <int TH, bool CONN8>
-__global__ void __launch_bounds__(256) k2_boundary(ImgView v, uint32_t nH, uint32_t nV) {
-    const uint32_t seg = blockIdx.x * 4u + (threadIdx.x >> 6);
+__device__ __forceinline__ void k2_segment(const ImgView &v, uint32_t seg, uint32_t nH) {
     const int lane = lane_id();
-    if (seg >= nH + nV) return;  // wave-uniform
     constexpr int RT = roots_per_tile(TH);
     const uint32_t TX = (uint32_t)v.tilesX;
     uint32_t a = kNone, b0 = kNone, b1 = kNone;
@@ -235,16 +229,17 @@ __global__ void __launch_bounds__(256) k2_boundary(ImgView v, uint32_t nH, uint3
     if (keep1) g_union(v.labels, v.n, a, b1);
 }
 
-// Link phase (Sec. II-C): the local merge left every tile's row masks and,
-// per run, its tile-local root with an edge flag.  Each flagged local root
-// is resolved once in the global forest (and, being rewritten with its final
-// value, compressed for the tiles that still walk through it); unflagged
-// roots are already final.  Output rows are written as full 256-byte lines.
+// ----------------------------------------------------------------- link
+
+// Link body for tile t (Sec. II-C): the local merge left the tile's row
+// masks and, per run, its tile-local root with an edge flag.  Each flagged
+// local root is resolved once in the global forest (and, being rewritten
+// with its final value, compressed for the tiles that still walk through
+// it); unflagged roots are already final.  Output rows are full 256-byte
+// lines.  Ends after a workgroup barrier.
 template <int TH, int NW>
-__global__ void __launch_bounds__(NW * 64) k3_link(ImgView v) {
+__device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *fin) {
     constexpr int RPW = TH / NW;
-    __shared__ uint32_t fin[TH * kTileW];
-    const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = (int)(t % (uint32_t)v.tilesX), ty = (int)(t / (uint32_t)v.tilesX);
     const int lane = lane_id();
     const int wave = (int)(threadIdx.x >> 6);
@@ -272,25 +267,129 @@ __global__ void __launch_bounds__(NW * 64) k3_link(ImgView v) {
     }
     __syncthreads();
     const int x = tx * kTileW + lane;
-    if (x >= v.W) return;
+    if (x < v.W) {
 #pragma unroll
-    for (int k = 0; k < RPW; ++k) {
-        const int y = ty * TH + wave * RPW + k;
-        if (y >= v.H) break;
-        uint32_t out = 0u;
-        if (rec[k] != kNone) {
-            const uint32_t root = rec[k] & ~(uint32_t)kSlotFlag;
-            out = ((rec[k] & kSlotFlag) ? fin[root] : global_index(v, tx, ty, TH, root)) + 1u;
+        for (int k = 0; k < RPW; ++k) {
+            const int y = ty * TH + wave * RPW + k;
+            if (y >= v.H) break;
+            uint32_t out = 0u;
+            if (rec[k] != kNone) {
+                const uint32_t root = rec[k] & ~(uint32_t)kSlotFlag;
+                out = ((rec[k] & kSlotFlag) ? fin[root] : global_index(v, tx, ty, TH, root)) + 1u;
+            }
+            v.labels[(size_t)y * (size_t)v.W + (size_t)x] = out;
         }
-        v.labels[(size_t)y * (size_t)v.W + (size_t)x] = out;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------ single-image kernels
+
+template <int TH, int NW, bool CONN8>
+__global__ void __launch_bounds__(NW * 64) k1_local_merge(ImgView v) {
+    __shared__ K1Lds<TH> sh;
+    k1_tile<TH, NW, CONN8>(v, xcd_remap(blockIdx.x, gridDim.x), sh);
+}
+
+template <int TH, bool CONN8>
+__global__ void __launch_bounds__(256) k2_boundary(ImgView v, uint32_t nH, uint32_t nV) {
+    const uint32_t seg = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (seg >= nH + nV) return;  // wave-uniform
+    k2_segment<TH, CONN8>(v, seg, nH);
+}
+
+template <int TH, int NW>
+__global__ void __launch_bounds__(NW * 64) k3_link(ImgView v) {
+    __shared__ uint32_t fin[TH * kTileW];
+    k3_tile<TH, NW>(v, xcd_remap(blockIdx.x, gridDim.x), fin);
+}
+
+// ------------------------------------------------------------ batch kernels
+
+// Image of global tile (or edge segment) g: the last descriptor whose base
+// is <= g (descriptors are in base order).
+__device__ __forceinline__ uint32_t batch_image_of(const BatchImage *d, uint32_t n, uint32_t g,
+                                                   bool seg) {
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        const uint32_t base = seg ? d[mid].seg_base : d[mid].tile_base;
+        if (base <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int TH>
+__device__ __forceinline__ ImgView batch_view(const BatchImage &b, const BatchWs &w) {
+    ImgView v;
+    v.img = b.img;
+    v.labels = b.labels;
+    v.masks = w.masks + (size_t)b.tile_base * 4;
+    v.roots = w.roots + (size_t)b.tile_base * roots_per_tile(TH);
+    v.rowmask = w.rowmask + (size_t)b.tile_base * TH;
+    v.slots = w.slots + (size_t)b.tile_base * TH * kSlotsPerRow;
+    v.pitch = b.pitch;
+    v.H = b.H;
+    v.W = b.W;
+    v.tilesX = b.tilesX;
+    v.tilesY = b.tilesY;
+    v.n = b.n;
+    v.aligned16 = b.aligned16;
+    return v;
+}
+
+// Local merge over all tiles of all images.  Workgroups pull global tile
+// indices from a device work queue (an atomic counter) until it runs dry;
+// the boundary kernel of the same call resets the counter for the next call.
+template <int TH, int NW, bool CONN8>
+__global__ void __launch_bounds__(NW * 64) k1_batch(const BatchHeader *hdr, const BatchImage *descs,
+                                                    BatchWs w, uint32_t *queue) {
+    __shared__ K1Lds<TH> sh;
+    __shared__ uint32_t next;
+    const uint32_t total = hdr->total_tiles, n = hdr->n_images;
+    while (true) {
+        if (threadIdx.x == 0) next = atomicAdd(&queue[0], 1u);
+        __syncthreads();
+        const uint32_t g = next;
+        __syncthreads();
+        if (g >= total) break;
+        const uint32_t i = batch_image_of(descs, n, g, false);
+        const ImgView v = batch_view<TH>(descs[i], w);
+        k1_tile<TH, NW, CONN8>(v, g - descs[i].tile_base, sh);
+    }
+}
+
+template <int TH, bool CONN8>
+__global__ void __launch_bounds__(256) k2_batch(const BatchHeader *hdr, const BatchImage *descs,
+                                                BatchWs w, uint32_t *queue) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) queue[0] = 0u;  // the local merge has finished
+    const uint32_t total = hdr->total_segs, n = hdr->n_images;
+    const uint32_t wave = threadIdx.x >> 6;
+    for (uint32_t s = blockIdx.x * 4u + wave; s < total; s += gridDim.x * 4u) {
+        const uint32_t i = batch_image_of(descs, n, s, true);
+        const ImgView v = batch_view<TH>(descs[i], w);
+        k2_segment<TH, CONN8>(v, s - descs[i].seg_base, descs[i].nH);
+    }
+}
+
+template <int TH, int NW>
+__global__ void __launch_bounds__(NW * 64) k3_batch(const BatchHeader *hdr, const BatchImage *descs,
+                                                    BatchWs w) {
+    __shared__ uint32_t fin[TH * kTileW];
+    const uint32_t total = hdr->total_tiles, n = hdr->n_images;
+    for (uint32_t g = xcd_remap(blockIdx.x, gridDim.x); g < total; g += gridDim.x) {
+        const uint32_t i = batch_image_of(descs, n, g, false);
+        const ImgView v = batch_view<TH>(descs[i], w);
+        k3_tile<TH, NW>(v, g - descs[i].tile_base, fin);
     }
 }
 
 // ---------------------------------------------------------------- launchers
 
-// Resident workgroups of a persistent kernel on the current device
-// (occupancy x compute units), cached per (device, kernel).
-[[maybe_unused]] static uint32_t resident_groups(const void *kernel, int threads) {
+// Resident workgroups of a kernel on the current device (occupancy x compute
+// units), cached per (device, kernel).
+static uint32_t resident_groups(const void *kernel, int threads) {
     static std::mutex mu;
     static std::map<std::pair<int, const void *>, uint32_t> cache;
     int dev = 0;
@@ -313,14 +412,8 @@ static hipError_t launch_plain_t(const ImgView &v, hipStream_t stream, hipEvent_
     const uint32_t tiles = (uint32_t)v.tilesX * (uint32_t)v.tilesY;
     const uint32_t nH = (uint32_t)v.tilesX * (uint32_t)(v.tilesY - 1);
     const uint32_t nV = (uint32_t)(v.tilesX - 1) * (uint32_t)v.tilesY;
-    // One workgroup per tile: with about as many tiles as resident slots, a
-    // persistent grid leaves a second round of tiles on a few workgroups
-    // while the rest of the chip idles.  The loop in the kernel only runs
-    // more than once for grids capped below the tile count.
-    const uint32_t grid1 = tiles;
     if (ev) (void)hipEventRecord(ev[0], stream);
-    hipLaunchKernelGGL((k1_local_merge<TH, NW, CONN8>), dim3(grid1), dim3(NW * 64), 0, stream, v,
-                       tiles);
+    hipLaunchKernelGGL((k1_local_merge<TH, NW, CONN8>), dim3(tiles), dim3(NW * 64), 0, stream, v);
     if (ev) (void)hipEventRecord(ev[1], stream);
     if (nH + nV > 0)
         hipLaunchKernelGGL((k2_boundary<TH, CONN8>), dim3((nH + nV + 3) / 4), dim3(256), 0, stream,
@@ -331,9 +424,17 @@ static hipError_t launch_plain_t(const ImgView &v, hipStream_t stream, hipEvent_
     return hipGetLastError();
 }
 
-template <int TH, int NW>
-static hipError_t launch_plain_c(const ImgView &v, int conn, hipStream_t s, hipEvent_t *ev) {
-    return conn == 8 ? launch_plain_t<TH, NW, true>(v, s, ev) : launch_plain_t<TH, NW, false>(v, s, ev);
+template <int TH, int NW, bool CONN8>
+static hipError_t launch_batch_t(const BatchHeader *hdr, const BatchImage *descs, const BatchWs &w,
+                                 uint32_t *queue, hipStream_t s) {
+    const uint32_t g1 = resident_groups((const void *)k1_batch<TH, NW, CONN8>, NW * 64);
+    const uint32_t g2 = resident_groups((const void *)k2_batch<TH, CONN8>, 256);
+    const uint32_t g3 = resident_groups((const void *)k3_batch<TH, NW>, NW * 64);
+    hipLaunchKernelGGL((k1_batch<TH, NW, CONN8>), dim3(g1), dim3(NW * 64), 0, s, hdr, descs, w,
+                       queue);
+    hipLaunchKernelGGL((k2_batch<TH, CONN8>), dim3(g2), dim3(256), 0, s, hdr, descs, w, queue);
+    hipLaunchKernelGGL((k3_batch<TH, NW>), dim3(g3), dim3(NW * 64), 0, s, hdr, descs, w);
+    return hipGetLastError();
 }
 
 bool config_supported(int th, int nw) {
@@ -345,12 +446,26 @@ bool config_supported(int th, int nw) {
     }
 }
 
+#define CCL_FOR_EACH_CONFIG(X)                                                              \
+    X(16, 1) X(16, 2) X(16, 4) X(16, 8) X(16, 16) X(32, 1) X(32, 2) X(32, 4) X(32, 8) X(32, 16) \
+        X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(64, 16)
+
 hipError_t launch_plain(const ImgView &v, int th, int nw, int conn, hipStream_t s, hipEvent_t *ev) {
-#define CCL_CASE(T, N) \
-    if (th == T && nw == N) return launch_plain_c<T, N>(v, conn, s, ev);
-    CCL_CASE(16, 1) CCL_CASE(16, 2) CCL_CASE(16, 4) CCL_CASE(16, 8) CCL_CASE(16, 16)
-    CCL_CASE(32, 1) CCL_CASE(32, 2) CCL_CASE(32, 4) CCL_CASE(32, 8) CCL_CASE(32, 16)
-    CCL_CASE(64, 1) CCL_CASE(64, 2) CCL_CASE(64, 4) CCL_CASE(64, 8) CCL_CASE(64, 16)
+#define CCL_CASE(T, N)                                                                   \
+    if (th == T && nw == N)                                                              \
+        return conn == 8 ? launch_plain_t<T, N, true>(v, s, ev) : launch_plain_t<T, N, false>(v, s, ev);
+    CCL_FOR_EACH_CONFIG(CCL_CASE)
+#undef CCL_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch(const BatchHeader *hdr, const BatchImage *descs, const BatchWs &w,
+                        uint32_t *queue, int th, int nw, int conn, hipStream_t s) {
+#define CCL_CASE(T, N)                                                                      \
+    if (th == T && nw == N)                                                                 \
+        return conn == 8 ? launch_batch_t<T, N, true>(hdr, descs, w, queue, s)              \
+                         : launch_batch_t<T, N, false>(hdr, descs, w, queue, s);
+    CCL_FOR_EACH_CONFIG(CCL_CASE)
 #undef CCL_CASE
     return hipErrorInvalidValue;
 }

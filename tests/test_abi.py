@@ -80,3 +80,45 @@ def test_workspace_size_formula():
         rowm = -(-tiles * th * 8 // 256) * 256
         slots = -(-tiles * th * 64 // 256) * 256
         assert binding.workspace_size(H, W, (th, 4 if th >= 4 else 1)) == masks + roots + rowm + slots
+
+
+def test_batch_validation_without_device():
+    lib = binding.load_library()
+    h = ctypes.c_void_p()
+    assert lib.ccl_ctx_create(None, None) == 1
+    opts = binding.CtxOpts(0, 100, binding.Config(0, 0), 1)
+    assert lib.ccl_ctx_create(ctypes.byref(h), ctypes.byref(opts)) == 1   # max_images < 1
+    opts = binding.CtxOpts(4, 0, binding.Config(0, 0), 1)
+    assert lib.ccl_ctx_create(ctypes.byref(h), ctypes.byref(opts)) == 1   # max_pixels < 1
+    assert lib.ccl_label_batch(None, None, 1, 8, None) == 1
+    assert lib.ccl_ctx_destroy(None) == 1
+
+
+def test_autotune_validation_without_device():
+    lib = binding.load_library()
+    best = binding.Config(0, 0)
+    assert lib.ccl_autotune(None, 8, 8, 8, 8, FAKE, 3, None, ctypes.byref(best), None) == 1
+    assert lib.ccl_autotune(FAKE, 8, 8, 8, 5, FAKE, 3, None, ctypes.byref(best), None) == 2
+    assert lib.ccl_autotune(FAKE, 8, 8, 8, 8, FAKE, 0, None, ctypes.byref(best), None) == 1
+
+
+def test_tuning_table_roundtrip(tmp_path):
+    binding.tuning_clear()
+    assert binding.tuning_get(4096, 4096, 8) == (32, 2)       # built-in default
+    src = tmp_path / "in.jsonl"
+    src.write_text('{"class": 24, "conn": 8, "tile_h": 64, "waves": 4, "ms": 0.150000}\n'
+                   '{"class": 20, "conn": 4, "tile_h": 16, "waves": 1, "ms": 0.020000}\n')
+    binding.tuning_load(str(src))
+    assert binding.tuning_get(4096, 4096, 8) == (64, 4)       # 2^24 pixels -> class 24
+    assert binding.tuning_get(4096, 4096, 4) == (32, 2)       # other connectivity: default
+    assert binding.tuning_get(1024, 1024, 4) == (16, 1)       # 2^20 pixels -> class 20
+    out = tmp_path / "out.jsonl"
+    binding.tuning_save(str(out))
+    lines = sorted(out.read_text().strip().splitlines())
+    assert len(lines) == 2 and '"tile_h": 64' in "".join(lines)
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text('{"class": 24, "conn": 8, "tile_h": 48, "waves": 4, "ms": 1.0}\n')
+    with pytest.raises(binding.CclError):
+        binding.tuning_load(str(bad))
+    binding.tuning_clear()
+    assert binding.tuning_get(4096, 4096, 8) == (32, 2)

@@ -1,0 +1,117 @@
+"""GPU parity of the batched form: every image of a batch must equal the
+oracle and the single-image entry point bit for bit, across repeated calls
+(graph replays, work-queue reuse) and ragged image sets."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_08180_amd import binding
+from paper_1708_08180_amd import workloads as wl
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+SMALL_SIZES = ((1, 1), (3, 70), (70, 3), (64, 64), (65, 129), (240, 320), (100, 333), (480, 640))
+
+
+def _mixed_images(n, seed, sizes=SMALL_SIZES):
+    rng = wl.rng_for(seed)
+    imgs = []
+    for i in range(n):
+        H, W = sizes[int(rng.integers(len(sizes)))]
+        if i % 3 == 0:
+            imgs.append(wl.bernoulli(H, W, float(rng.uniform(0.2, 0.8)), seed * 1000 + i))
+        elif i % 3 == 1:
+            imgs.append(wl.smoothed_noise(H, W, float(rng.uniform(2, 8)), seed * 1000 + i))
+        else:
+            imgs.append(wl.bernoulli(H, W, 0.5, seed * 1000 + i, g=3))
+    return imgs
+
+
+def _run(ctx, imgs, conn):
+    import torch
+
+    d = [torch.from_numpy(np.ascontiguousarray(im)).cuda() for im in imgs]
+    outs = ctx.label(d, conn)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy().view(np.uint32) for o in outs]
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+@pytest.mark.parametrize("conn", [8, 4])
+def test_batch_matches_oracle(conn, use_graph):
+    ctx = binding.BatchContext(64, 64 * 480 * 640, use_graph=use_graph)
+    for call, seed in enumerate((1, 2, 3)):       # several calls: queue reset, graph replay
+        imgs = _mixed_images(40 + 7 * call, seed)
+        say("batch call %d conn=%d graph=%s n=%d" % (call, conn, use_graph, len(imgs)))
+        got = _run(ctx, imgs, conn)
+        for k, (im, g) in enumerate(zip(imgs, got)):
+            want = oracle.label(im, conn)
+            assert np.array_equal(g, want), "image %d (%dx%d) differs" % (k, im.shape[0], im.shape[1])
+    ctx.close()
+
+
+@pytest.mark.parametrize("config", [(16, 1), (32, 2), (64, 4), (64, 16)])
+def test_batch_tile_configs(config):
+    ctx = binding.BatchContext(16, 16 * 480 * 640, config=config)
+    imgs = _mixed_images(16, 9)
+    for conn in (8, 4):
+        got = _run(ctx, imgs, conn)
+        for im, g in zip(imgs, got):
+            assert np.array_equal(g, oracle.label(im, conn))
+    ctx.close()
+
+
+def test_batch_equals_single_image_path():
+    import torch
+
+    imgs = _mixed_images(24, 5, sizes=((720, 1280), (1080, 1920), (240, 320)))
+    ctx = binding.BatchContext(24, sum(im.size for im in imgs))
+    got = _run(ctx, imgs, 8)
+    for im, g in zip(imgs, got):
+        single = binding.label_plain(torch.from_numpy(im).cuda(), 8)
+        torch.cuda.synchronize()
+        assert np.array_equal(g, single.cpu().numpy().view(np.uint32))
+    ctx.close()
+
+
+def test_batch_single_image_and_sizes_change():
+    ctx = binding.BatchContext(8, 8 * 1080 * 1920)
+    for seed, n in ((11, 1), (12, 8), (13, 2), (14, 1)):
+        imgs = _mixed_images(n, seed, sizes=((1080, 1920), (17, 33), (1, 1)))
+        for conn in (8, 4):
+            got = _run(ctx, imgs, conn)
+            for im, g in zip(imgs, got):
+                assert np.array_equal(g, oracle.label(im, conn))
+    ctx.close()
+
+
+def test_batch_capacity_errors():
+    import torch
+
+    ctx = binding.BatchContext(2, 64 * 64)
+    d = [torch.zeros((64, 64), dtype=torch.uint8, device="cuda") for _ in range(3)]
+    with pytest.raises(binding.CclError) as e:
+        ctx.label(d, 8)
+    assert e.value.status == 6
+    big = [torch.zeros((1024, 1024), dtype=torch.uint8, device="cuda")]
+    with pytest.raises(binding.CclError) as e:
+        ctx.label(big, 8)
+    assert e.value.status == 6
+    ctx.close()
+
+
+def test_autotune_records_a_supported_config():
+    import torch
+
+    img = wl.bernoulli(512, 512, 0.5, 3)
+    d = torch.from_numpy(img).cuda()
+    binding.tuning_clear()
+    best, ms = binding.autotune(d, 8, reps=2)
+    assert best in {(t, w) for t in (16, 32, 64) for w in (1, 2, 4, 8, 16)}
+    assert ms > 0
+    assert binding.tuning_get(512, 512, 8) == best
+    out = binding.label_plain(d, 8)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), oracle.label(img, 8))
+    binding.tuning_clear()

@@ -147,3 +147,27 @@ def test_repeated_runs_are_exact(config):
             for rep in range(8):
                 got = gpu_label(img, conn, config=config)
                 assert np.array_equal(got, want), "config %s conn %d rep %d" % (config, conn, rep)
+
+
+def test_stream_ordering_with_torch_work():
+    # the library's kernels must run in order with torch work on the same
+    # (non-default) stream: torch writes the image right before the call and
+    # reads the labels right after, with no synchronization in between
+    import torch
+
+    img = wl.bernoulli(1024, 1536, 0.5, 21)
+    want = oracle.label(img, 8)
+    host = torch.from_numpy(img).pin_memory()
+    from paper_1708_08180_amd import binding
+
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        d = torch.zeros((1024, 1536), dtype=torch.uint8, device="cuda")
+        out = torch.full((1024, 1536), -7, dtype=torch.int32, device="cuda")
+        for _ in range(3):
+            d.zero_()
+            d.copy_(host, non_blocking=True)
+            binding.label_plain(d, 8, out=out, stream=s)
+            res = out.to("cpu", non_blocking=True)
+            s.synchronize()
+            assert np.array_equal(res.numpy().view(np.uint32), want)
