@@ -194,6 +194,71 @@ int ccl_ctx_destroy(ccl_ctx *ctx);
 int ccl_label_batch(ccl_ctx *ctx, const ccl_image_desc *descs, int32_t n, int32_t connectivity,
                     void *stream);
 
+/* ----------------------------------------------------------------- serve
+ *
+ * A request loop for frames that arrive over time (the served form).  Frames
+ * are device-resident images; the server owns the label buffers: a pool of
+ * slots of max_frame_pixels labels each, as many as fit in hbm_budget bytes.
+ * A scheduler thread admits submitted frames in arrival order while a slot
+ * is free, and hands the admitted frames to every idle worker as one batch
+ * (each worker has its own HIP stream, batch context and captured graph), so
+ * frames that arrive while other batches run are admitted and start on the
+ * next free worker while those batches are still on the device.  Labels and
+ * their contract are exactly those of ccl_label_2d for every frame.
+ * plain = 1 selects the per-frame baseline: one worker, one ccl_label_2d
+ * call per frame, same admission and bookkeeping.
+ */
+typedef struct ccl_server ccl_server;
+
+typedef struct ccl_server_opts {
+    int32_t n_workers;         /* >= 1 device streams the batches overlap on */
+    int32_t max_batch;         /* most frames per batch (1 in plain mode) */
+    int64_t max_frame_pixels;  /* largest H*W a frame may have (slot size) */
+    int64_t max_batch_pixels;  /* most pixels per batch (>= max_frame_pixels) */
+    int64_t hbm_budget;        /* bytes of label slots (>= one slot) */
+    int32_t connectivity;      /* 4 or 8, for every frame */
+    ccl_config cfg;            /* tile configuration, {0,0} = library choice */
+    int32_t use_graph;         /* replay captured graphs per worker */
+    int32_t plain;             /* per-frame baseline (n_workers = max_batch = 1) */
+} ccl_server_opts;
+
+/* One finished frame.  labels points into the server's slot `slot` and
+ * stays valid until ccl_server_release(slot).  Times are host steady-clock
+ * nanoseconds: submission, slot granted, batch launched, completion seen
+ * (t_done_ns = -1 when the frame's launch failed). */
+typedef struct ccl_frame_result {
+    uint64_t tag;
+    uint32_t *labels;
+    int32_t slot;
+    int64_t t_submit_ns, t_admit_ns, t_launch_ns, t_done_ns;
+} ccl_frame_result;
+
+/* Create a server on the current device and start its scheduler thread. */
+int ccl_server_create(ccl_server **out, const ccl_server_opts *opts);
+
+/* Number of label slots the HBM budget bought. */
+int ccl_server_slots(const ccl_server *s, int32_t *n_slots);
+
+/* Enqueue one frame (device image, H x W, row pitch in bytes); returns at
+ * once.  `tag` is returned with the result.  The image must stay unchanged
+ * until the frame completes.  CCL_ERR_CAPACITY if H*W > max_frame_pixels. */
+int ccl_server_submit(ccl_server *s, const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
+                      uint64_t tag);
+
+/* Move up to `max` finished frames into out[] (completion order); *n_out
+ * receives the count.  Returns the first error the loop met, else CCL_OK. */
+int ccl_server_poll(ccl_server *s, ccl_frame_result *out, int32_t max, int32_t *n_out);
+
+/* Give a finished frame's label slot back for admission. */
+int ccl_server_release(ccl_server *s, int32_t slot);
+
+/* Frames submitted and not yet finished. */
+int ccl_server_pending(ccl_server *s, int64_t *in_flight);
+
+/* Stop admitting, drop frames still waiting for a slot, wait for every
+ * admitted frame to finish, and free everything. */
+int ccl_server_destroy(ccl_server *s);
+
 /* ---------------------------------------------------------------- tuning
  *
  * The tile configuration of ccl_label_2d is taken from a process-wide table

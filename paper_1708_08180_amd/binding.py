@@ -38,6 +38,19 @@ class CtxOpts(ctypes.Structure):
                 ("cfg", Config), ("use_graph", ctypes.c_int32)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("n_workers", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("max_frame_pixels", ctypes.c_int64), ("max_batch_pixels", ctypes.c_int64),
+                ("hbm_budget", ctypes.c_int64), ("connectivity", ctypes.c_int32),
+                ("cfg", Config), ("use_graph", ctypes.c_int32), ("plain", ctypes.c_int32)]
+
+
+class FrameResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("labels", ctypes.c_void_p), ("slot", ctypes.c_int32),
+                ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_launch_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
+
+
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _I64 = ctypes.c_int64
@@ -64,6 +77,13 @@ SIGNATURES = {
     "ccl_tuning_save": (ctypes.c_int, [ctypes.c_char_p]),
     "ccl_tuning_load": (ctypes.c_int, [ctypes.c_char_p]),
     "ccl_tuning_clear": (None, []),
+    "ccl_server_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ServerOpts)]),
+    "ccl_server_slots": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "ccl_server_submit": (ctypes.c_int, [_P, _P, _I32, _I32, _I64, ctypes.c_uint64]),
+    "ccl_server_poll": (ctypes.c_int, [_P, ctypes.POINTER(FrameResult), _I32, ctypes.POINTER(ctypes.c_int32)]),
+    "ccl_server_release": (ctypes.c_int, [_P, _I32]),
+    "ccl_server_pending": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "ccl_server_destroy": (ctypes.c_int, [_P]),
 }
 
 
@@ -328,3 +348,61 @@ def tuning_load(path: str):
 
 def tuning_clear():
     load_library().ccl_tuning_clear()
+
+
+class Server:
+    """Owns a ccl_server (request loop with HBM-budget admission and
+    continuous batching over several worker streams)."""
+
+    def __init__(self, max_frame_pixels: int, hbm_budget: int, n_workers: int = 2,
+                 max_batch: int = 8, max_batch_pixels: int = None, conn: int = 8, config=None,
+                 use_graph: bool = True, plain: bool = False):
+        lib = load_library()
+        if plain:
+            n_workers, max_batch = 1, 1
+        if max_batch_pixels is None:
+            max_batch_pixels = max_frame_pixels * max_batch
+        opts = ServerOpts(int(n_workers), int(max_batch), int(max_frame_pixels), int(max_batch_pixels),
+                          int(hbm_budget), int(conn), Config(*(config if config else (0, 0))),
+                          1 if use_graph else 0, 1 if plain else 0)
+        h = ctypes.c_void_p()
+        _check(lib.ccl_server_create(ctypes.byref(h), ctypes.byref(opts)), "ccl_server_create")
+        self._h = h
+        self._buf = (FrameResult * 4096)()
+        n = ctypes.c_int32(0)
+        _check(lib.ccl_server_slots(self._h, ctypes.byref(n)), "ccl_server_slots")
+        self.n_slots = int(n.value)
+
+    def submit(self, img, tag: int):
+        """Submit a 2D uint8 device tensor (must stay unchanged until done)."""
+        H, W = img.shape
+        return load_library().ccl_server_submit(self._h, img.data_ptr(), H, W, _pitch(img), int(tag))
+
+    def poll(self):
+        """Finished frames as tuples (tag, labels_ptr, slot, t_submit, t_admit, t_launch, t_done)."""
+        n = ctypes.c_int32(0)
+        rc = load_library().ccl_server_poll(self._h, self._buf, len(self._buf), ctypes.byref(n))
+        out = [(r.tag, r.labels, r.slot, r.t_submit_ns, r.t_admit_ns, r.t_launch_ns, r.t_done_ns)
+               for r in self._buf[:n.value]]
+        _check(rc, "ccl_server_poll")
+        return out
+
+    def release(self, slot: int):
+        _check(load_library().ccl_server_release(self._h, int(slot)), "ccl_server_release")
+
+    def pending(self) -> int:
+        v = ctypes.c_int64(0)
+        _check(load_library().ccl_server_pending(self._h, ctypes.byref(v)), "ccl_server_pending")
+        return int(v.value)
+
+    def close(self):
+        if self._h:
+            rc = load_library().ccl_server_destroy(self._h)
+            self._h = None
+            _check(rc, "ccl_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
