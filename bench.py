@@ -8,8 +8,10 @@ already resident in HBM; K steps run back to back on one stream between
 two synchronizations and are timed with HIP events.
 
 Prints ONE JSON line with the throughput (Gpixels/s), the roofline of the
-dominant kernel (per-phase HIP events over a second timed pass), and the
-CPU oracle timed on the host as a reported baseline.
+dominant kernel (per-phase HIP events over a second timed pass), the CPU
+oracle timed on the host as a reported baseline, and (unless skipped) the
+batched form (512 mixed images per call against 512 plain calls) and the
+served form (camera streams; frames/s at equal p99 latency).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        [--workload headline|sweep|structured] [--no-cpu-baseline]
@@ -118,6 +120,104 @@ def cpu_baseline(img, conn, gpu_labels, seconds):
             "parity_vs_gpu": parity}
 
 
+def bench_batch(args, torch, binding, log):
+    """Batched form: 512 mixed images per call vs 512 plain per-image calls."""
+    import numpy as np
+
+    from paper_1708_08180_amd import workloads as wl
+
+    t0 = time.perf_counter()
+    specs = wl.batch_spec(args.batch_n, 40000)
+    imgs = wl.batch_images(specs, workers=min(8, os.cpu_count() or 1))
+    log("[bench] batch: rendered %d images in %.1f s" % (len(imgs), time.perf_counter() - t0))
+    d_imgs = [torch.from_numpy(im).cuda() for im in imgs]
+    outs = [torch.empty(im.shape, dtype=torch.int32, device="cuda") for im in imgs]
+    px = sum(im.size for im in imgs)
+    ctx = binding.BatchContext(len(imgs), px, use_graph=True)
+    descs = ctx.descs(d_imgs, outs)
+    lib = binding.load_library()
+    stream = torch.cuda.current_stream()
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    for _ in range(3):
+        ctx.label(d_imgs, args.conn, outs=outs, descs=descs)
+    torch.cuda.synchronize()
+    reps = args.batch_reps
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        ctx.label(d_imgs, args.conn, outs=outs, descs=descs)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms_batch = a.elapsed_time(b) / reps
+    # plain path: one ccl_label_2d per image, back to back on one stream
+    calls = [(im.data_ptr(), im.shape[0], im.shape[1], im.shape[1], args.conn, o.data_ptr(), sh)
+             for im, o in zip(d_imgs, outs)]
+    for c in calls:
+        lib.ccl_label_2d(*c)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        for c in calls:
+            lib.ccl_label_2d(*c)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = a.elapsed_time(b) / reps
+    # parity of a sample against the oracle (host), and the oracle as baseline
+    res = {"images": len(imgs), "gpixels": round(px / 1e9, 4),
+           "batched_ms": round(ms_batch, 4), "batched_fps": round(len(imgs) / ms_batch * 1e3, 1),
+           "batched_gpix_s": round(px / ms_batch / 1e6, 2),
+           "plain_ms": round(ms_plain, 4), "plain_fps": round(len(imgs) / ms_plain * 1e3, 1),
+           "plain_gpix_s": round(px / ms_plain / 1e6, 2),
+           "speedup_vs_plain": round(ms_plain / ms_batch, 3)}
+    if not args.no_cpu_baseline:
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+
+        ctx.label(d_imgs, args.conn, outs=outs, descs=descs)
+        torch.cuda.synchronize()
+        sample = list(range(0, len(imgs), max(1, len(imgs) // 24)))
+        cores = min(16, os.cpu_count() or 1)
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(cores) as ex:
+            want = list(ex.map(lambda k: oracle.label(imgs[k], args.conn), sample))
+        dt = time.perf_counter() - t0
+        spx = sum(imgs[k].size for k in sample)
+        ok = all(np.array_equal(outs[k].cpu().numpy().view(np.uint32), w) for k, w in zip(sample, want))
+        res["cpu_baseline"] = {"value": round(spx / dt / 1e9, 5), "unit": "Gpixels/s", "cores": cores,
+                               "kind": "oracle", "sample": "%d of the %d images, one per thread" % (len(sample), len(imgs)),
+                               "parity_vs_gpu": bool(ok)}
+    ctx.close()
+    del d_imgs, outs
+    return res
+
+
+def bench_serve(args, torch, log):
+    """Served form: 4 cameras (2x1080p, 2x2160p), Poisson arrivals; frames/s and
+    p50/p99 latency of the batched request loop against the plain per-frame loop."""
+    from paper_1708_08180_amd import serve
+
+    rings = serve.make_rings(ring=8)
+    sat_plain = serve.saturation_fps(rings, plain=True, conn=args.conn, n_frames=300)
+    sat_batch = serve.saturation_fps(rings, plain=False, conn=args.conn, n_frames=600)
+    log("[bench] serve: saturation plain %.0f fps, batched %.0f fps" % (sat_plain, sat_batch))
+    dur = args.serve_seconds
+    plain_pts = [serve.run(rings, f * sat_plain, dur, plain=True, conn=args.conn).as_dict()
+                 for f in (0.25, 0.5, 0.75, 0.9)]
+    batch_pts = []
+    for f in (0.25, 0.5, 0.75, 0.9, 1.0, 1.25, 1.5, 2.0, 2.5, 3.0):
+        if f * sat_plain > 0.95 * sat_batch:
+            break
+        batch_pts.append(serve.run(rings, f * sat_plain, dur, plain=False, conn=args.conn).as_dict())
+    bar = plain_pts[-1]["p99_ms"]
+    ok = [p for p in batch_pts if p["p99_ms"] <= bar]
+    best = max(ok, key=lambda p: p["fps"]) if ok else None
+    return {"cameras": "2x1920x1080 + 2x3840x2160, Poisson arrivals",
+            "plain_saturation_fps": round(sat_plain, 1), "batched_saturation_fps": round(sat_batch, 1),
+            "p99_bar_ms": bar, "plain_fps_at_bar": plain_pts[-1]["fps"],
+            "batched_fps_at_equal_p99": best["fps"] if best else None,
+            "plain": plain_pts, "batched": batch_pts}
+
+
 def make_workload(name):
     from paper_1708_08180_amd import workloads as wl
 
@@ -143,6 +243,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--config", default=None, help="tile_h,waves (default: library choice)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-form measurement")
+    ap.add_argument("--batch-n", type=int, default=512)
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 64 MiB device-to-device copy (a known-size kernel "
                          "for scaling HBM byte counters)")
@@ -152,7 +257,7 @@ def main():
     if args.gpus != 1 or world != 1:
         print("bench.py: this build measures one GPU; --gpus %d (WORLD_SIZE=%d) is not supported. "
               "Images are independent, so several GPUs would each label their own images; "
-              "see the sharding notes in the design document." % (args.gpus, world), file=sys.stderr)
+              "a single image would shard into row bands with one seam exchange." % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -262,6 +367,12 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on the host (about %.0f s)" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(head["img"], args.conn, head["labels"], args.cpu_seconds)
+    if args.workload == "headline" and not args.no_batch:
+        log("[bench] batched form")
+        out["batch"] = bench_batch(args, torch, binding, log)
+    if args.workload == "headline" and not args.no_serve:
+        log("[bench] served form")
+        out["serve"] = bench_serve(args, torch, log)
     print(json.dumps(out), flush=True)
 
 

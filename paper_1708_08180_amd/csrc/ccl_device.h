@@ -365,14 +365,21 @@ __device__ __forceinline__ PairMasks pair_masks(uint64_t d, uint64_t u) {
 // atomicMin on its node); every other root it touches is joined to that one
 // by a real union, which is rare.  Only after a row that had one are the
 // row's roots re-resolved, so `ra` always holds true roots.
+// rinfo[r] (written here, one byte per row): number of runs in bits 0..5,
+// bit 6 = the row's first run starts at column 0, bit 7 = its last run ends
+// at column 63.
 template <int TH, int RPW, bool CONN8>
-__device__ __forceinline__ void sweep_band(uint32_t *par, uint8_t *col, const uint64_t *msk,
-                                           int wave, int lane) {
+__device__ __forceinline__ void sweep_band(uint32_t *par, uint8_t *col, uint8_t *rinfo,
+                                           const uint64_t *msk, int wave, int lane) {
     uint32_t ra = kNone;
     uint64_t u = 0;
+    uint64_t m[RPW];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) m[k] = uniform64(msk[wave * RPW + k]);
+#pragma unroll
     for (int k = 0; k < RPW; ++k) {
         const int r = wave * RPW + k;
-        const uint64_t d = uniform64(msk[r]);
+        const uint64_t d = m[k];
         const uint64_t S = run_starts(d);
         const bool fg = lane_in(d), isS = lane_in(S);
         const uint32_t node = (uint32_t)(r * kSlotsPerRow) + bits_below(S) - (isS ? 0u : 1u);
@@ -380,6 +387,8 @@ __device__ __forceinline__ void sweep_band(uint32_t *par, uint8_t *col, const ui
             lds_st(&par[node], node);
             col[node] = (uint8_t)lane;
         }
+        if (lane == 0)
+            rinfo[r] = (uint8_t)(__popcll(S) | ((d & 1ull) ? 0x40 : 0) | ((d >> 63) ? 0x80 : 0));
         uint32_t md = fg ? node : kNone;
         if (k > 0) {
             const PairMasks p = pair_masks<CONN8>(d, u);

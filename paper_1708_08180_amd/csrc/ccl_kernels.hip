@@ -45,6 +45,7 @@ struct K1Lds {
     uint32_t par[TH * kSlotsPerRow];  // run-indexed parents
     uint8_t col[TH * kSlotsPerRow];   // first column of every run
     uint64_t msk[TH];                 // row masks
+    uint8_t rinfo[TH];                // runs per row | first run at column 0 | last at 63
 };
 
 // Kernel 1 body for tile t of image v.  Ends after a workgroup barrier, so
@@ -60,6 +61,7 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH> 
     uint32_t *par = sh.par;
     uint8_t *col = sh.col;
     uint64_t *msk = sh.msk;
+    uint8_t *rinfo = sh.rinfo;
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t TX = (uint32_t)v.tilesX;
     const int tx = (int)(t % TX), ty = (int)(t / TX);
@@ -72,37 +74,33 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH> 
             ((uint16_t *)msk)[c] = (uint16_t)nonzero_bytes16(load_chunk(v, tx, ty, TH, c >> 2, c & 3));
     }
     __syncthreads();
-    sweep_band<TH, RPW, CONN8>(par, col, msk, wave, lane);
+    sweep_band<TH, RPW, CONN8>(par, col, rinfo, msk, wave, lane);
     if (NW > 1) {
         __syncthreads();
         if (wave > 0) merge_seam<CONN8>(par, msk, wave * RPW);
     }
     __syncthreads();
 
-    // node-parallel finish: compress (each node written by its owner only, so
-    // par[n] is the root afterwards), mark edge-touching roots, emit records
+    // node-parallel finish.  Pass 1: every node finds its root (read-only
+    // walk) and its owner alone stores it, so par[n] is the root afterwards;
+    // roots are never stored to, so the edge marks ORed into them survive
+    // (a marked root still reads as a root: its value is >= its index).
     const bool hasUp = ty > 0, hasDown = ty + 1 < v.tilesY;
     const bool hasLeft = tx > 0, hasRight = tx + 1 < v.tilesX;
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
         const int n = tid + i * NT;
         if (n >= NODES) break;
-        const uint64_t d = msk[n >> 5];
-        if ((n & 31) < __popcll(run_starts(d))) lds_st(&par[n], lds_root(par, (uint32_t)n));
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-        const int n = tid + i * NT;
-        if (n >= NODES) break;
         const int r = n >> 5, k = n & 31;
-        const uint64_t d = msk[r];
-        const int runs = __popcll(run_starts(d));
+        const uint32_t info = rinfo[r];
+        const int runs = (int)(info & 63u);
         if (k >= runs) continue;
+        const uint32_t root = lds_root(par, (uint32_t)n);
+        if (root != (uint32_t)n) lds_st(&par[n], root);
         const bool edge = (r == 0 && hasUp) || (r == TH - 1 && hasDown) ||
-                          (k == 0 && (d & 1ull) && hasLeft) ||
-                          (k == runs - 1 && (d >> 63) && hasRight);
-        if (edge) atomicOr(&par[lds_ld(&par[n]) & kIdx], kFlag);
+                          (k == 0 && (info & 0x40u) && hasLeft) ||
+                          (k == runs - 1 && (info & 0x80u) && hasRight);
+        if (edge) atomicOr(&par[root], kFlag);
     }
     __syncthreads();
     uint16_t *sl = v.slots + (size_t)t * TH * kSlotsPerRow;
@@ -110,8 +108,7 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH> 
     for (int i = 0; i < NPT; ++i) {
         const int n = tid + i * NT;
         if (n >= NODES) break;
-        const uint64_t d = msk[n >> 5];
-        if ((n & 31) >= __popcll(run_starts(d))) continue;
+        if ((n & 31) >= (int)(rinfo[n >> 5] & 63u)) continue;
         const uint32_t root = lds_ld(&par[n]) & kIdx;
         const uint32_t flag = lds_ld(&par[root]) & kFlag;
         const uint32_t rpix = (root >> 5) * kTileW + col[root];
@@ -248,14 +245,14 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *
     uint64_t m[RPW];
     uint32_t rec[RPW];
 #pragma unroll
-    for (int k = 0; k < RPW; ++k) m[k] = rm[wave * RPW + k];
+    for (int k = 0; k < RPW; ++k) m[k] = uniform64(rm[wave * RPW + k]);
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
         const int r = wave * RPW + k;
         rec[k] = kNone;
-        if (bit(m[k], lane)) {
-            const uint64_t starts = m[k] & ~(m[k] << 1);
-            const int rank = __popcll(starts & ((2ull << lane) - 1ull)) - 1;
+        if (lane_in(m[k])) {
+            const uint64_t S = run_starts(m[k]);
+            const uint32_t rank = bits_below(S) - (lane_in(S) ? 0u : 1u);
             rec[k] = sl[r * kSlotsPerRow + rank];
         }
     }

@@ -181,9 +181,12 @@ def make_image(spec: ImageSpec) -> np.ndarray:
 def batch_images(specs, workers: int = 0):
     """Render a list of ``ImageSpec``; ``workers`` > 1 spreads them over processes."""
     if workers and workers > 1 and len(specs) > 1:
+        import multiprocessing
         from concurrent.futures import ProcessPoolExecutor
 
-        with ProcessPoolExecutor(max_workers=workers) as ex:
+        # spawn: the workers must not inherit a parent's GPU state
+        with ProcessPoolExecutor(max_workers=workers,
+                                 mp_context=multiprocessing.get_context("spawn")) as ex:
             return list(ex.map(make_image, specs, chunksize=4))
     return [make_image(s) for s in specs]
 
