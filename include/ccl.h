@@ -136,9 +136,10 @@ int ccl_label_2d_timed(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
 /* ------------------------------------------------------------------ batch
  *
  * A context labels many images of different sizes in one call (the batched
- * form): persistent kernels run each phase over the tiles of all images, the
- * local merge pulling tiles from a device work queue, and the three launches
- * are replayed from a captured hipGraph.  Results are bit-identical to
+ * form): each phase is one launch over the tiles (edge segments) of all
+ * images, numbered consecutively, with grids sized for the call; the three
+ * launches can be replayed from a hipGraph whose kernel nodes are updated
+ * with each call's grids and arguments.  Results are bit-identical to
  * ccl_label_2d on each image.
  */
 typedef struct ccl_ctx ccl_ctx;
@@ -158,8 +159,10 @@ typedef struct ccl_image_desc {
  *             workspace is sized for it with room for partial tiles.
  * cfg         tile configuration for every call ({0,0} = the library's
  *             choice for an image of max_pixels / max_images pixels).
- * use_graph   nonzero: record the three launches once per connectivity into
- *             a hipGraph and replay it (needs a non-null stream). */
+ * use_graph   nonzero: build one three-node hipGraph per connectivity and
+ *             replay it; when a call's grids or arguments differ from the
+ *             previous call's, the nodes are updated first (after waiting
+ *             for the context's previous call to finish on the device). */
 typedef struct ccl_ctx_opts {
     int32_t max_images;
     int64_t max_pixels;
@@ -171,8 +174,8 @@ typedef struct ccl_ctx_opts {
  * a pinned staging area once.  *out receives the handle. */
 int ccl_ctx_create(ccl_ctx **out, const ccl_ctx_opts *opts);
 
-/* Synchronize the context's last staging copy and free everything it owns.
- * The caller must have synchronized the streams it labeled on. */
+/* Wait for the context's last call on the device and free everything it
+ * owns. */
 int ccl_ctx_destroy(ccl_ctx *ctx);
 
 /*
@@ -189,7 +192,9 @@ int ccl_ctx_destroy(ccl_ctx *ctx);
  * the kernels of a call read the context's device buffers until they
  * finish and the next call overwrites them, so use one stream per context
  * (or order the streams yourself).  The staging area is reused only after
- * the previous call's copy has completed.
+ * the previous call's copy has completed.  The call blocks only for those
+ * two waits (staging reuse, graph update); back-to-back calls on the same
+ * batch shape never block.
  */
 int ccl_label_batch(ccl_ctx *ctx, const ccl_image_desc *descs, int32_t n, int32_t connectivity,
                     void *stream);
@@ -201,7 +206,7 @@ int ccl_label_batch(ccl_ctx *ctx, const ccl_image_desc *descs, int32_t n, int32_
  * slots of max_frame_pixels labels each, as many as fit in hbm_budget bytes.
  * A scheduler thread admits submitted frames in arrival order while a slot
  * is free, and hands the admitted frames to every idle worker as one batch
- * (each worker has its own HIP stream, batch context and captured graph), so
+ * (each worker has its own HIP stream, batch context and graph), so
  * frames that arrive while other batches run are admitted and start on the
  * next free worker while those batches are still on the device.  Labels and
  * their contract are exactly those of ccl_label_2d for every frame.
@@ -218,7 +223,7 @@ typedef struct ccl_server_opts {
     int64_t hbm_budget;        /* bytes of label slots (>= one slot) */
     int32_t connectivity;      /* 4 or 8, for every frame */
     ccl_config cfg;            /* tile configuration, {0,0} = library choice */
-    int32_t use_graph;         /* replay captured graphs per worker */
+    int32_t use_graph;         /* workers replay their batch graphs */
     int32_t plain;             /* per-frame baseline (n_workers = max_batch = 1) */
 } ccl_server_opts;
 

@@ -254,7 +254,7 @@ def shutdown():
 
 
 class BatchContext:
-    """Owns a ccl_ctx (fixed capacity, device buffers, captured graphs)."""
+    """Owns a ccl_ctx (fixed capacity, device buffers, batch graphs)."""
 
     def __init__(self, max_images: int, max_pixels: int, config=None, use_graph: bool = True):
         lib = load_library()

@@ -1,10 +1,11 @@
 // Batched form: a context with fixed capacity labels many images per call.
 //
-// Per call the host writes one descriptor per image (tile and edge-segment
-// bases from prefix sums) into a pinned staging area, copies it to the
-// device on the caller's stream, and replays (or launches) the three batch
-// kernels.  Everything the kernels touch lives in buffers allocated once at
-// context creation, so the captured hipGraph stays valid for every call.
+// Per call the host writes one descriptor per image plus the images' tile
+// and edge-segment bases (prefix sums) into a pinned staging area, copies
+// them to the device on the caller's stream, and runs the three batch
+// kernels with grids sized for that call: directly, or by replaying a
+// three-node hipGraph whose kernel nodes get the call's grid and arguments.
+// Every buffer the kernels touch is allocated once at context creation.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -15,36 +16,90 @@
 
 using namespace ccl;
 
+namespace {
+
+struct GraphSet {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t node[3] = {nullptr, nullptr, nullptr};
+    BatchArgs args{};
+    unsigned grid[3] = {0, 0, 0};
+};
+
+}  // namespace
+
 struct ccl_ctx {
     int dev = 0;
     int th = 0, nw = 0;
     int32_t max_images = 0;
     uint64_t max_tiles = 0, max_segs = 0;
-    size_t desc_bytes = 0;       // header + max_images descriptors
-    char *d_desc = nullptr;      // device copy of header + descriptors
+    size_t desc_bytes = 0;       // descriptors + tile bases + segment bases
+    char *d_desc = nullptr;      // device copy of that area
     char *h_staging = nullptr;   // pinned host staging of the same layout
     void *d_ws = nullptr;
     BatchWs ws{};
-    uint32_t *d_queue = nullptr;
-    hipEvent_t staged = nullptr;  // recorded after each staging copy
-    bool staged_pending = false;
+    BatchKernels kern[2]{};      // connectivity 4, 8
+    hipEvent_t staged = nullptr;    // recorded after each staging copy
+    hipEvent_t launched = nullptr;  // recorded after each call's kernels
+    bool staged_pending = false, launched_pending = false;
     int use_graph = 0;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};  // connectivity 4, 8
-    bool warmed[2] = {false, false};
+    GraphSet gs[2];
 };
 
 namespace {
 
+// Offsets of the three arrays for n images (64-byte aligned).
+void desc_layout(int32_t n, size_t *off_tb, size_t *off_sb, size_t *bytes) {
+    *off_tb = align_up((size_t)n * sizeof(BatchImage), 64);
+    *off_sb = *off_tb + align_up((size_t)n * sizeof(uint32_t), 64);
+    *bytes = *off_sb + (size_t)n * sizeof(uint32_t);
+}
+
 void free_ctx(ccl_ctx *c) {
     if (!c) return;
-    for (auto &g : c->graph)
-        if (g) (void)hipGraphExecDestroy(g);
+    for (GraphSet &g : c->gs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
     if (c->staged) (void)hipEventDestroy(c->staged);
+    if (c->launched) (void)hipEventDestroy(c->launched);
     if (c->d_desc) (void)hipFree(c->d_desc);
     if (c->d_ws) (void)hipFree(c->d_ws);
-    if (c->d_queue) (void)hipFree(c->d_queue);
     if (c->h_staging) (void)hipHostFree(c->h_staging);
     delete c;
+}
+
+void node_params(const BatchKernels &k, int j, unsigned grid, void **args, hipKernelNodeParams *p) {
+    std::memset(p, 0, sizeof(*p));
+    p->func = (void *)(j == 0 ? k.k1 : j == 1 ? k.k2 : k.k3);
+    p->gridDim = dim3(grid);
+    p->blockDim = dim3(j == 0 ? k.block1 : j == 1 ? k.block2 : k.block3);
+    p->sharedMemBytes = 0;
+    p->kernelParams = args;
+    p->extra = nullptr;
+}
+
+// Build and instantiate the graph K1 -> K2 -> K3 with the given arguments.
+hipError_t build_graph(GraphSet &g, const BatchKernels &k, const BatchArgs &a,
+                       const unsigned grid[3]) {
+    BatchArgs copy = a;
+    void *args[] = {&copy};
+    hipError_t e = hipGraphCreate(&g.graph, 0);
+    for (int j = 0; j < 3 && e == hipSuccess; ++j) {
+        hipKernelNodeParams p;
+        node_params(k, j, grid[j], args, &p);
+        e = hipGraphAddKernelNode(&g.node[j], g.graph, j ? &g.node[j - 1] : nullptr, j ? 1 : 0, &p);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        g = GraphSet{};
+        return e;
+    }
+    g.args = a;
+    for (int j = 0; j < 3; ++j) g.grid[j] = grid[j];
+    return hipSuccess;
 }
 
 }  // namespace
@@ -84,7 +139,19 @@ int ccl_ctx_create(ccl_ctx **out, const ccl_ctx_opts *opts) {
         return CCL_ERR_TOO_LARGE;
     }
     c->max_segs = 2 * c->max_tiles;
-    c->desc_bytes = sizeof(BatchHeader) + (size_t)c->max_images * sizeof(BatchImage);
+    if (!batch_kernels(c->th, c->nw, 4, &c->kern[0]) || !batch_kernels(c->th, c->nw, 8, &c->kern[1])) {
+        delete c;
+        return CCL_ERR_UNSUPPORTED;
+    }
+    // one workgroup per tile: the grid's thread count must fit in 32 bits
+    if (c->max_tiles * (uint64_t)c->kern[1].block1 > 0xFFFFFFFFull) {
+        delete c;
+        return CCL_ERR_TOO_LARGE;
+    }
+    {
+        size_t tb, sb;
+        desc_layout(c->max_images, &tb, &sb, &c->desc_bytes);
+    }
 
     const size_t T = (size_t)c->max_tiles;
     const size_t mb = align_up(T * 4 * sizeof(uint64_t), 256);
@@ -93,10 +160,9 @@ int ccl_ctx_create(ccl_ctx **out, const ccl_ctx_opts *opts) {
     const size_t sb = align_up(T * (size_t)c->th * kSlotsPerRow * sizeof(uint16_t), 256);
     if ((e = hipMalloc(&c->d_ws, mb + rb + rmb + sb)) != hipSuccess ||
         (e = hipMalloc(&c->d_desc, c->desc_bytes)) != hipSuccess ||
-        (e = hipMalloc(&c->d_queue, 256)) != hipSuccess ||
         (e = hipHostMalloc(&c->h_staging, c->desc_bytes, hipHostMallocDefault)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->staged, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipMemset(c->d_queue, 0, 256)) != hipSuccess) {
+        (e = hipEventCreateWithFlags(&c->launched, hipEventDisableTiming)) != hipSuccess) {
         (void)hipGetLastError();
         free_ctx(c);
         return e == hipErrorOutOfMemory ? CCL_ERR_OUT_OF_MEMORY : fail_hip(e);
@@ -113,6 +179,7 @@ int ccl_ctx_create(ccl_ctx **out, const ccl_ctx_opts *opts) {
 int ccl_ctx_destroy(ccl_ctx *ctx) {
     if (!ctx) return CCL_ERR_INVALID_ARG;
     if (ctx->staged_pending) (void)hipEventSynchronize(ctx->staged);
+    if (ctx->launched_pending) (void)hipEventSynchronize(ctx->launched);
     free_ctx(ctx);
     return CCL_OK;
 }
@@ -149,8 +216,11 @@ int ccl_label_batch(ccl_ctx *ctx, const ccl_image_desc *descs, int32_t n, int32_
         if (e != hipSuccess) return fail_hip(e);
         ctx->staged_pending = false;
     }
-    BatchHeader *hh = (BatchHeader *)ctx->h_staging;
-    BatchImage *hd = (BatchImage *)(ctx->h_staging + sizeof(BatchHeader));
+    size_t off_tb, off_sb, bytes;
+    desc_layout(n, &off_tb, &off_sb, &bytes);
+    BatchImage *hd = (BatchImage *)ctx->h_staging;
+    uint32_t *htb = (uint32_t *)(ctx->h_staging + off_tb);
+    uint32_t *hsb = (uint32_t *)(ctx->h_staging + off_sb);
     uint32_t tb = 0, sb = 0;
     for (int32_t i = 0; i < n; ++i) {
         const ccl_image_desc &d = descs[i];
@@ -168,52 +238,68 @@ int ccl_label_batch(ccl_ctx *ctx, const ccl_image_desc *descs, int32_t n, int32_
         b.seg_base = sb;
         b.nH = (uint32_t)b.tilesX * (uint32_t)(b.tilesY - 1);
         b.nV = (uint32_t)(b.tilesX - 1) * (uint32_t)b.tilesY;
+        htb[i] = tb;
+        hsb[i] = sb;
         tb += (uint32_t)b.tilesX * (uint32_t)b.tilesY;
         sb += b.nH + b.nV;
     }
-    hh->n_images = (uint32_t)n;
-    hh->total_tiles = tb;
-    hh->total_segs = sb;
-    hh->pad = 0;
-    const size_t bytes = sizeof(BatchHeader) + (size_t)n * sizeof(BatchImage);
     e = hipMemcpyAsync(ctx->d_desc, ctx->h_staging, bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return fail_hip(e);
     e = hipEventRecord(ctx->staged, s);
     if (e != hipSuccess) return fail_hip(e);
     ctx->staged_pending = true;
 
-    const BatchHeader *dh = (const BatchHeader *)ctx->d_desc;
-    const BatchImage *dd = (const BatchImage *)(ctx->d_desc + sizeof(BatchHeader));
+    BatchArgs a{};
+    a.descs = (const BatchImage *)ctx->d_desc;
+    a.tile_base = (const uint32_t *)(ctx->d_desc + off_tb);
+    a.seg_base = (const uint32_t *)(ctx->d_desc + off_sb);
+    a.w = ctx->ws;
+    a.n = (uint32_t)n;
+    a.tiles = tb;
+    a.segs = sb;
+    a.pad = 0;
     const int gi = connectivity == 8 ? 1 : 0;
-    if (ctx->use_graph && s != nullptr && ctx->warmed[gi]) {
-        if (!ctx->graph[gi]) {
-            hipGraph_t g = nullptr;
-            e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    const BatchKernels &k = ctx->kern[gi];
+    const unsigned segs_grid = (sb + k.segs_per_group - 1) / k.segs_per_group;
+    const unsigned grid[3] = {tb, segs_grid ? segs_grid : 1u, tb};
+    if (ctx->use_graph) {
+        GraphSet &g = ctx->gs[gi];
+        if (!g.exec) {
+            e = build_graph(g, k, a, grid);
             if (e != hipSuccess) return fail_hip(e);
-            const hipError_t le = launch_batch(dh, dd, ctx->ws, ctx->d_queue, ctx->th, ctx->nw,
-                                               connectivity, s);
-            e = hipStreamEndCapture(s, &g);
-            if (le != hipSuccess) {
-                if (g) (void)hipGraphDestroy(g);
-                return fail_hip(le);
+        } else if (std::memcmp(&g.args, &a, sizeof(a)) != 0 || g.grid[0] != grid[0] ||
+                   g.grid[1] != grid[1] || g.grid[2] != grid[2]) {
+            // an earlier launch of this graph may not have read its arguments yet
+            if (ctx->launched_pending) {
+                e = hipEventSynchronize(ctx->launched);
+                if (e != hipSuccess) return fail_hip(e);
+                ctx->launched_pending = false;
             }
-            if (e != hipSuccess) return fail_hip(e);
-            e = hipGraphInstantiate(&ctx->graph[gi], g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) {
-                ctx->graph[gi] = nullptr;
-                return fail_hip(e);
+            BatchArgs copy = a;
+            void *args[] = {&copy};
+            for (int j = 0; j < 3; ++j) {
+                hipKernelNodeParams p;
+                node_params(k, j, grid[j], args, &p);
+                e = hipGraphExecKernelNodeSetParams(g.exec, g.node[j], &p);
+                if (e != hipSuccess) return fail_hip(e);
             }
+            g.args = a;
+            for (int j = 0; j < 3; ++j) g.grid[j] = grid[j];
         }
-        e = hipGraphLaunch(ctx->graph[gi], s);
+        e = hipGraphLaunch(g.exec, s);
         if (e != hipSuccess) return fail_hip(e);
-        return CCL_OK;
+    } else {
+        void *args[] = {&a};
+        const unsigned blk[3] = {k.block1, k.block2, k.block3};
+        const void *fn[3] = {k.k1, k.k2, k.k3};
+        for (int j = 0; j < 3; ++j) {
+            e = hipLaunchKernel(fn[j], dim3(grid[j]), dim3(blk[j]), args, 0, s);
+            if (e != hipSuccess) return fail_hip(e);
+        }
     }
-    // direct launches (also the first call per connectivity, which sizes the
-    // persistent grids outside any capture)
-    e = launch_batch(dh, dd, ctx->ws, ctx->d_queue, ctx->th, ctx->nw, connectivity, s);
+    e = hipEventRecord(ctx->launched, s);
     if (e != hipSuccess) return fail_hip(e);
-    ctx->warmed[gi] = true;
+    ctx->launched_pending = true;
     return CCL_OK;
 }
 

@@ -80,16 +80,23 @@ struct BatchImage {
     uint32_t nH, nV;
 };
 
-struct BatchHeader {
-    uint32_t n_images, total_tiles, total_segs, pad;
-};
-
 // Workspace of a batch context, indexed by global tile.
 struct BatchWs {
     uint64_t *masks;
     uint32_t *roots;
     uint64_t *rowmask;
     uint16_t *slots;
+};
+
+// Kernel argument of the three batch kernels (one call).  tile_base and
+// seg_base are the n descriptors' bases as two dense ascending arrays, so a
+// workgroup finds its image with one coalesced read.
+struct BatchArgs {
+    const BatchImage *descs;
+    const uint32_t *tile_base;
+    const uint32_t *seg_base;
+    BatchWs w;
+    uint32_t n, tiles, segs, pad;
 };
 
 // ------------------------------------------------------------------ helpers

@@ -13,11 +13,16 @@ namespace ccl {
 // True when (tile_h, waves) names a compiled kernel configuration.
 bool config_supported(int th, int nw);
 
-// Enqueue the three batch phases (persistent kernels) on `s`.  hdr and
-// descs are device pointers; queue is a zeroed device counter that the
-// boundary kernel re-zeroes for the next call.
-hipError_t launch_batch(const BatchHeader *hdr, const BatchImage *descs, const BatchWs &w,
-                        uint32_t *queue, int th, int nw, int conn, hipStream_t s);
+// The three batch kernels of one configuration.  Each takes one BatchArgs
+// by value.  Grids: local merge and link one workgroup (block1 / block3
+// threads) per tile; boundary analysis one workgroup (block2 threads) per
+// segs_per_group edge segments.
+struct BatchKernels {
+    const void *k1, *k2, *k3;
+    unsigned block1, block2, block3;
+    unsigned segs_per_group;
+};
+bool batch_kernels(int th, int nw, int conn, BatchKernels *out);
 
 // Enqueue the three phases for one image on `s`.  With ev != nullptr,
 // ev[0..3] are recorded before phase 1, between the phases and after phase 3.

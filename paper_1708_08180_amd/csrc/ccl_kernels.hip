@@ -16,11 +16,8 @@
 //
 // The per-tile and per-edge bodies are device functions shared by the
 // single-image kernels (one workgroup per tile / per four edges) and the
-// batch kernels (persistent workgroups over the tiles of all images; the
-// local merge pulls tiles from a device work queue).
-#include <map>
-#include <mutex>
-#include <utility>
+// batch kernels (the same bodies over one global numbering of the tiles and
+// edge segments of all images).
 
 #include "ccl_device.h"
 #include "ccl_internal.h"
@@ -303,18 +300,20 @@ __global__ void __launch_bounds__(NW * 64) k3_link(ImgView v) {
 
 // ------------------------------------------------------------ batch kernels
 
-// Image of global tile (or edge segment) g: the last descriptor whose base
-// is <= g (descriptors are in base order).
-__device__ __forceinline__ uint32_t batch_image_of(const BatchImage *d, uint32_t n, uint32_t g,
-                                                   bool seg) {
-    uint32_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        const uint32_t base = seg ? d[mid].seg_base : d[mid].tile_base;
-        if (base <= g) lo = mid;
-        else hi = mid - 1;
+// Image that owns global item g (a tile or an edge segment): the last image
+// whose base is <= g, i.e. the number of bases <= g minus one.  Images with
+// no edge segments share their seg_base with the next image, and the count
+// then lands on the last of them, the one that owns the segment.  Each lane
+// compares one base per 64 images.
+__device__ __forceinline__ uint32_t batch_image_of(const uint32_t *base, uint32_t n, uint32_t g) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t cnt = 0;
+#pragma unroll 4
+    for (uint32_t j = 0; j < n; j += 64) {
+        const uint32_t k = j + lane;
+        cnt += (uint32_t)__popcll(__ballot(k < n && base[k] <= g));
     }
-    return lo;
+    return cnt - 1u;
 }
 
 template <int TH>
@@ -336,73 +335,40 @@ __device__ __forceinline__ ImgView batch_view(const BatchImage &b, const BatchWs
     return v;
 }
 
-// Local merge over all tiles of all images.  Workgroups pull global tile
-// indices from a device work queue (an atomic counter) until it runs dry;
-// the boundary kernel of the same call resets the counter for the next call.
+// The batch kernels are the single-image ones over the global tile (edge
+// segment) numbering of all images: one workgroup per tile for the local
+// merge and the link, four edge segments per workgroup for the boundary
+// analysis.  The host sizes the grids for every call.
 template <int TH, int NW, bool CONN8>
-__global__ void __launch_bounds__(NW * 64) k1_batch(const BatchHeader *hdr, const BatchImage *descs,
-                                                    BatchWs w, uint32_t *queue) {
+__global__ void __launch_bounds__(NW * 64) k1_batch(BatchArgs a) {
     __shared__ K1Lds<TH> sh;
-    __shared__ uint32_t next;
-    const uint32_t total = hdr->total_tiles, n = hdr->n_images;
-    while (true) {
-        if (threadIdx.x == 0) next = atomicAdd(&queue[0], 1u);
-        __syncthreads();
-        const uint32_t g = next;
-        __syncthreads();
-        if (g >= total) break;
-        const uint32_t i = batch_image_of(descs, n, g, false);
-        const ImgView v = batch_view<TH>(descs[i], w);
-        k1_tile<TH, NW, CONN8>(v, g - descs[i].tile_base, sh);
-    }
+    const uint32_t g = xcd_remap(blockIdx.x, gridDim.x);
+    if (g >= a.tiles) return;  // workgroup-uniform
+    const uint32_t i = batch_image_of(a.tile_base, a.n, g);
+    const BatchImage &d = a.descs[i];
+    k1_tile<TH, NW, CONN8>(batch_view<TH>(d, a.w), g - d.tile_base, sh);
 }
 
 template <int TH, bool CONN8>
-__global__ void __launch_bounds__(256) k2_batch(const BatchHeader *hdr, const BatchImage *descs,
-                                                BatchWs w, uint32_t *queue) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) queue[0] = 0u;  // the local merge has finished
-    const uint32_t total = hdr->total_segs, n = hdr->n_images;
-    const uint32_t wave = threadIdx.x >> 6;
-    for (uint32_t s = blockIdx.x * 4u + wave; s < total; s += gridDim.x * 4u) {
-        const uint32_t i = batch_image_of(descs, n, s, true);
-        const ImgView v = batch_view<TH>(descs[i], w);
-        k2_segment<TH, CONN8>(v, s - descs[i].seg_base, descs[i].nH);
-    }
+__global__ void __launch_bounds__(256) k2_batch(BatchArgs a) {
+    const uint32_t s = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (s >= a.segs) return;  // wave-uniform
+    const uint32_t i = batch_image_of(a.seg_base, a.n, s);
+    const BatchImage &d = a.descs[i];
+    k2_segment<TH, CONN8>(batch_view<TH>(d, a.w), s - d.seg_base, d.nH);
 }
 
 template <int TH, int NW>
-__global__ void __launch_bounds__(NW * 64) k3_batch(const BatchHeader *hdr, const BatchImage *descs,
-                                                    BatchWs w) {
+__global__ void __launch_bounds__(NW * 64) k3_batch(BatchArgs a) {
     __shared__ uint32_t fin[TH * kTileW];
-    const uint32_t total = hdr->total_tiles, n = hdr->n_images;
-    for (uint32_t g = xcd_remap(blockIdx.x, gridDim.x); g < total; g += gridDim.x) {
-        const uint32_t i = batch_image_of(descs, n, g, false);
-        const ImgView v = batch_view<TH>(descs[i], w);
-        k3_tile<TH, NW>(v, g - descs[i].tile_base, fin);
-    }
+    const uint32_t g = xcd_remap(blockIdx.x, gridDim.x);
+    if (g >= a.tiles) return;  // workgroup-uniform
+    const uint32_t i = batch_image_of(a.tile_base, a.n, g);
+    const BatchImage &d = a.descs[i];
+    k3_tile<TH, NW>(batch_view<TH>(d, a.w), g - d.tile_base, fin);
 }
 
 // ---------------------------------------------------------------- launchers
-
-// Resident workgroups of a kernel on the current device (occupancy x compute
-// units), cached per (device, kernel).
-static uint32_t resident_groups(const void *kernel, int threads) {
-    static std::mutex mu;
-    static std::map<std::pair<int, const void *>, uint32_t> cache;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 1024;
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find(std::make_pair(dev, kernel));
-    if (it != cache.end()) return it->second;
-    int cus = 0, per_cu = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
-        cus <= 0 || per_cu <= 0)
-        return 1024;
-    const uint32_t g = (uint32_t)cus * (uint32_t)per_cu;
-    cache[std::make_pair(dev, kernel)] = g;
-    return g;
-}
 
 template <int TH, int NW, bool CONN8>
 static hipError_t launch_plain_t(const ImgView &v, hipStream_t stream, hipEvent_t *ev) {
@@ -422,16 +388,13 @@ static hipError_t launch_plain_t(const ImgView &v, hipStream_t stream, hipEvent_
 }
 
 template <int TH, int NW, bool CONN8>
-static hipError_t launch_batch_t(const BatchHeader *hdr, const BatchImage *descs, const BatchWs &w,
-                                 uint32_t *queue, hipStream_t s) {
-    const uint32_t g1 = resident_groups((const void *)k1_batch<TH, NW, CONN8>, NW * 64);
-    const uint32_t g2 = resident_groups((const void *)k2_batch<TH, CONN8>, 256);
-    const uint32_t g3 = resident_groups((const void *)k3_batch<TH, NW>, NW * 64);
-    hipLaunchKernelGGL((k1_batch<TH, NW, CONN8>), dim3(g1), dim3(NW * 64), 0, s, hdr, descs, w,
-                       queue);
-    hipLaunchKernelGGL((k2_batch<TH, CONN8>), dim3(g2), dim3(256), 0, s, hdr, descs, w, queue);
-    hipLaunchKernelGGL((k3_batch<TH, NW>), dim3(g3), dim3(NW * 64), 0, s, hdr, descs, w);
-    return hipGetLastError();
+static void batch_kernels_t(BatchKernels *k) {
+    k->k1 = (const void *)k1_batch<TH, NW, CONN8>;
+    k->k2 = (const void *)k2_batch<TH, CONN8>;
+    k->k3 = (const void *)k3_batch<TH, NW>;
+    k->block1 = k->block3 = NW * 64;
+    k->block2 = 256;
+    k->segs_per_group = 4;
 }
 
 bool config_supported(int th, int nw) {
@@ -456,15 +419,16 @@ hipError_t launch_plain(const ImgView &v, int th, int nw, int conn, hipStream_t 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch(const BatchHeader *hdr, const BatchImage *descs, const BatchWs &w,
-                        uint32_t *queue, int th, int nw, int conn, hipStream_t s) {
-#define CCL_CASE(T, N)                                                                      \
-    if (th == T && nw == N)                                                                 \
-        return conn == 8 ? launch_batch_t<T, N, true>(hdr, descs, w, queue, s)              \
-                         : launch_batch_t<T, N, false>(hdr, descs, w, queue, s);
+bool batch_kernels(int th, int nw, int conn, BatchKernels *out) {
+#define CCL_CASE(T, N)                                                                   \
+    if (th == T && nw == N) {                                                            \
+        if (conn == 8) batch_kernels_t<T, N, true>(out);                                 \
+        else batch_kernels_t<T, N, false>(out);                                          \
+        return true;                                                                     \
+    }
     CCL_FOR_EACH_CONFIG(CCL_CASE)
 #undef CCL_CASE
-    return hipErrorInvalidValue;
+    return false;
 }
 
 }  // namespace ccl

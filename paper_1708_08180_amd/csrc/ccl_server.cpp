@@ -5,7 +5,7 @@
 //   1. admits waiting frames in arrival order while a label slot is free
 //      (the slot pool is carved out of the HBM budget given at creation),
 //   2. hands admitted frames to every idle worker -- each worker owns a HIP
-//      stream, a batch context and its captured graph -- as one batch of up
+//      stream, a batch context and its graph -- as one batch of up
 //      to max_batch frames (continuous batching: frames that arrive while
 //      other batches run are admitted and launched on the next free worker,
 //      so their work overlaps on the device),

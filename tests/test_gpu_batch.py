@@ -1,6 +1,7 @@
 """GPU parity of the batched form: every image of a batch must equal the
 oracle and the single-image entry point bit for bit, across repeated calls
-(graph replays, work-queue reuse) and ragged image sets."""
+(graph replays and node updates, calls queued back to back) and ragged
+image sets."""
 import numpy as np
 import pytest
 
@@ -41,7 +42,7 @@ def _run(ctx, imgs, conn):
 @pytest.mark.parametrize("conn", [8, 4])
 def test_batch_matches_oracle(conn, use_graph):
     ctx = binding.BatchContext(64, 64 * 480 * 640, use_graph=use_graph)
-    for call, seed in enumerate((1, 2, 3)):       # several calls: queue reset, graph replay
+    for call, seed in enumerate((1, 2, 3)):       # several calls: graph replay and node updates
         imgs = _mixed_images(40 + 7 * call, seed)
         say("batch call %d conn=%d graph=%s n=%d" % (call, conn, use_graph, len(imgs)))
         got = _run(ctx, imgs, conn)
@@ -83,6 +84,34 @@ def test_batch_single_image_and_sizes_change():
             got = _run(ctx, imgs, conn)
             for im, g in zip(imgs, got):
                 assert np.array_equal(g, oracle.label(im, conn))
+    ctx.close()
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_back_to_back_calls_with_changing_shapes(use_graph):
+    """Calls queued without a host synchronization in between, alternating
+    batch shapes (so graph nodes are updated while earlier calls may still
+    be queued) and repeating one shape (pure replays); every call has its
+    own outputs and is checked after one final synchronization."""
+    import torch
+
+    ctx = binding.BatchContext(48, 48 * 480 * 640, use_graph=use_graph)
+    plan = [(21, 5), (22, 40), (21, 5), (21, 5), (23, 1), (24, 17), (22, 40)]
+    sets = {}
+    for seed, n in set(plan):
+        sets[seed] = _mixed_images(n, seed)
+    dev = {seed: [torch.from_numpy(np.ascontiguousarray(im)).cuda() for im in imgs]
+           for seed, imgs in sets.items()}
+    torch.cuda.synchronize()
+    results = []
+    for k, (seed, n) in enumerate(plan):
+        conn = 8 if k % 2 == 0 else 4
+        say("queued call %d seed=%d n=%d conn=%d graph=%s" % (k, seed, n, conn, use_graph))
+        results.append((seed, conn, ctx.label(dev[seed], conn)))
+    torch.cuda.synchronize()
+    for seed, conn, outs in results:
+        for im, o in zip(sets[seed], outs):
+            assert np.array_equal(o.cpu().numpy().view(np.uint32), oracle.label(im, conn))
     ctx.close()
 
 
