@@ -1,7 +1,7 @@
 // Batched form: a context with fixed capacity labels many images per call.
 //
-// Per call the host writes one descriptor per image plus the images' tile
-// and edge-segment bases (prefix sums) into a pinned staging area, copies
+// Per call the host writes one descriptor per image plus the images' first
+// global tiles (prefix sums) into a pinned staging area, copies
 // them to the device on the caller's stream, and runs the three batch
 // kernels with grids sized for that call: directly, or by replaying a
 // three-node hipGraph whose kernel nodes get the call's grid and arguments.
@@ -32,8 +32,8 @@ struct ccl_ctx {
     int dev = 0;
     int th = 0, nw = 0;
     int32_t max_images = 0;
-    uint64_t max_tiles = 0, max_segs = 0;
-    size_t desc_bytes = 0;       // descriptors + tile bases + segment bases
+    uint64_t max_tiles = 0;
+    size_t desc_bytes = 0;       // descriptors + tile bases + coarse bases
     char *d_desc = nullptr;      // device copy of that area
     char *h_staging = nullptr;   // pinned host staging of the same layout
     void *d_ws = nullptr;
@@ -48,11 +48,12 @@ struct ccl_ctx {
 
 namespace {
 
-// Offsets of the three arrays for n images (64-byte aligned).
-void desc_layout(int32_t n, size_t *off_tb, size_t *off_sb, size_t *bytes) {
+// Offsets of the three arrays for n images (64-byte aligned): descriptors,
+// tile bases, and every 64th tile base.
+void desc_layout(int32_t n, size_t *off_tb, size_t *off_cb, size_t *bytes) {
     *off_tb = align_up((size_t)n * sizeof(BatchImage), 64);
-    *off_sb = *off_tb + align_up((size_t)n * sizeof(uint32_t), 64);
-    *bytes = *off_sb + (size_t)n * sizeof(uint32_t);
+    *off_cb = *off_tb + align_up((size_t)n * sizeof(uint32_t), 64);
+    *bytes = *off_cb + (size_t)((n + 63) / 64) * sizeof(uint32_t);
 }
 
 void free_ctx(ccl_ctx *c) {
@@ -138,7 +139,6 @@ int ccl_ctx_create(ccl_ctx **out, const ccl_ctx_opts *opts) {
         delete c;
         return CCL_ERR_TOO_LARGE;
     }
-    c->max_segs = 2 * c->max_tiles;
     if (!batch_kernels(c->th, c->nw, 4, &c->kern[0]) || !batch_kernels(c->th, c->nw, 8, &c->kern[1])) {
         delete c;
         return CCL_ERR_UNSUPPORTED;
@@ -158,7 +158,8 @@ int ccl_ctx_create(ccl_ctx **out, const ccl_ctx_opts *opts) {
     const size_t rb = align_up(T * (size_t)roots_per_tile(c->th) * sizeof(uint32_t), 256);
     const size_t rmb = align_up(T * (size_t)c->th * sizeof(uint64_t), 256);
     const size_t sb = align_up(T * (size_t)c->th * kSlotsPerRow * sizeof(uint16_t), 256);
-    if ((e = hipMalloc(&c->d_ws, mb + rb + rmb + sb)) != hipSuccess ||
+    const size_t ib = align_up(T * sizeof(uint32_t), 256);
+    if ((e = hipMalloc(&c->d_ws, mb + rb + rmb + sb + ib)) != hipSuccess ||
         (e = hipMalloc(&c->d_desc, c->desc_bytes)) != hipSuccess ||
         (e = hipHostMalloc(&c->h_staging, c->desc_bytes, hipHostMallocDefault)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->staged, hipEventDisableTiming)) != hipSuccess ||
@@ -172,6 +173,7 @@ int ccl_ctx_create(ccl_ctx **out, const ccl_ctx_opts *opts) {
     c->ws.roots = (uint32_t *)(base + mb);
     c->ws.rowmask = (uint64_t *)(base + mb + rb);
     c->ws.slots = (uint16_t *)(base + mb + rb + rmb);
+    c->ws.tile_img = (uint32_t *)(base + mb + rb + rmb + sb);
     *out = c;
     return CCL_OK;
 }
@@ -198,7 +200,7 @@ int ccl_label_batch(ccl_ctx *ctx, const ccl_image_desc *descs, int32_t n, int32_
     if (dev != ctx->dev) return CCL_ERR_INVALID_ARG;
 
     // validate everything and total the tiles before touching the staging area
-    uint64_t tiles = 0, segs = 0;
+    uint64_t tiles = 0;
     for (int32_t i = 0; i < n; ++i) {
         const ccl_image_desc &d = descs[i];
         const int rc = validate_image(d.img, d.H, d.W, d.pitch, d.labels);
@@ -206,9 +208,8 @@ int ccl_label_batch(ccl_ctx *ctx, const ccl_image_desc *descs, int32_t n, int32_
         const uint64_t tx = (uint64_t)((d.W + kTileW - 1) / kTileW);
         const uint64_t ty = (uint64_t)((d.H + ctx->th - 1) / ctx->th);
         tiles += tx * ty;
-        segs += tx * (ty - 1) + (tx - 1) * ty;
     }
-    if (tiles > ctx->max_tiles || segs > ctx->max_segs) return CCL_ERR_CAPACITY;
+    if (tiles > ctx->max_tiles) return CCL_ERR_CAPACITY;
 
     hipStream_t s = (hipStream_t)stream;
     if (ctx->staged_pending) {
@@ -216,12 +217,12 @@ int ccl_label_batch(ccl_ctx *ctx, const ccl_image_desc *descs, int32_t n, int32_
         if (e != hipSuccess) return fail_hip(e);
         ctx->staged_pending = false;
     }
-    size_t off_tb, off_sb, bytes;
-    desc_layout(n, &off_tb, &off_sb, &bytes);
+    size_t off_tb, off_cb, bytes;
+    desc_layout(n, &off_tb, &off_cb, &bytes);
     BatchImage *hd = (BatchImage *)ctx->h_staging;
     uint32_t *htb = (uint32_t *)(ctx->h_staging + off_tb);
-    uint32_t *hsb = (uint32_t *)(ctx->h_staging + off_sb);
-    uint32_t tb = 0, sb = 0;
+    uint32_t *hcb = (uint32_t *)(ctx->h_staging + off_cb);
+    uint32_t tb = 0;
     for (int32_t i = 0; i < n; ++i) {
         const ccl_image_desc &d = descs[i];
         BatchImage &b = hd[i];
@@ -235,13 +236,10 @@ int ccl_label_batch(ccl_ctx *ctx, const ccl_image_desc *descs, int32_t n, int32_
         b.n = (uint32_t)((uint64_t)d.H * (uint64_t)d.W);
         b.aligned16 = (((uintptr_t)d.img & 15u) == 0 && (d.pitch & 15) == 0) ? 1 : 0;
         b.tile_base = tb;
-        b.seg_base = sb;
-        b.nH = (uint32_t)b.tilesX * (uint32_t)(b.tilesY - 1);
-        b.nV = (uint32_t)(b.tilesX - 1) * (uint32_t)b.tilesY;
+        b.pad = 0;
         htb[i] = tb;
-        hsb[i] = sb;
+        if ((i & 63) == 0) hcb[i >> 6] = tb;
         tb += (uint32_t)b.tilesX * (uint32_t)b.tilesY;
-        sb += b.nH + b.nV;
     }
     e = hipMemcpyAsync(ctx->d_desc, ctx->h_staging, bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return fail_hip(e);
@@ -252,16 +250,13 @@ int ccl_label_batch(ccl_ctx *ctx, const ccl_image_desc *descs, int32_t n, int32_
     BatchArgs a{};
     a.descs = (const BatchImage *)ctx->d_desc;
     a.tile_base = (const uint32_t *)(ctx->d_desc + off_tb);
-    a.seg_base = (const uint32_t *)(ctx->d_desc + off_sb);
+    a.coarse = (const uint32_t *)(ctx->d_desc + off_cb);
     a.w = ctx->ws;
     a.n = (uint32_t)n;
     a.tiles = tb;
-    a.segs = sb;
-    a.pad = 0;
     const int gi = connectivity == 8 ? 1 : 0;
     const BatchKernels &k = ctx->kern[gi];
-    const unsigned segs_grid = (sb + k.segs_per_group - 1) / k.segs_per_group;
-    const unsigned grid[3] = {tb, segs_grid ? segs_grid : 1u, tb};
+    const unsigned grid[3] = {tb, (tb + k.tiles_per_group2 - 1) / k.tiles_per_group2, tb};
     if (ctx->use_graph) {
         GraphSet &g = ctx->gs[gi];
         if (!g.exec) {

@@ -66,8 +66,8 @@ struct ImgView {
 
 // One image of a batch as the batch kernels see it (device descriptor).
 // Tiles of all images are numbered consecutively: image i owns global tiles
-// [tile_base, tile_base + tilesX*tilesY) and edge segments
-// [seg_base, seg_base + nH + nV); its workspace lives at those tile offsets.
+// [tile_base, tile_base + tilesX*tilesY), and its workspace lives at those
+// tile offsets.
 struct BatchImage {
     const uint8_t *img;
     uint32_t *labels;
@@ -76,27 +76,29 @@ struct BatchImage {
     int32_t tilesX, tilesY;
     uint32_t n;
     int32_t aligned16;
-    uint32_t tile_base, seg_base;
-    uint32_t nH, nV;
+    uint32_t tile_base, pad;
 };
 
-// Workspace of a batch context, indexed by global tile.
+// Workspace of a batch context, indexed by global tile.  tile_img[g] is the
+// image that owns global tile g (written by the local merge, read by the
+// two later phases).
 struct BatchWs {
     uint64_t *masks;
     uint32_t *roots;
     uint64_t *rowmask;
     uint16_t *slots;
+    uint32_t *tile_img;
 };
 
-// Kernel argument of the three batch kernels (one call).  tile_base and
-// seg_base are the n descriptors' bases as two dense ascending arrays, so a
-// workgroup finds its image with one coalesced read.
+// Kernel argument of the three batch kernels (one call).  tile_base holds
+// the n images' first global tiles (ascending) and coarse every 64th of
+// them, so the local merge finds a tile's image with two coalesced reads.
 struct BatchArgs {
     const BatchImage *descs;
     const uint32_t *tile_base;
-    const uint32_t *seg_base;
+    const uint32_t *coarse;
     BatchWs w;
-    uint32_t n, tiles, segs, pad;
+    uint32_t n, tiles;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -133,31 +135,6 @@ __device__ __forceinline__ uint32_t g_ld(const uint32_t *p) {
 }
 __device__ __forceinline__ uint32_t g_min(uint32_t *p, uint32_t v) {
     return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Which neighbours in the line above a cell must be merged with it so that
-// every (lower run, upper run) pair that touches is merged exactly once: the
-// pair is handled by the leftmost lower cell adjacent to the upper run.
-//   start : the cell is the first of its run in its own line
-//   cL/cM/cR : the cells above-left / above / above-right are foreground and
-//              belong to this edge's candidate set
-//   sameLM / sameMR : those upper neighbours belong to one run
-struct Plan { bool l, m, r; };
-
-template <bool CONN8>
-__device__ __forceinline__ Plan plan_pairs(bool start, bool cL, bool cM, bool cR, bool sameLM,
-                                           bool sameMR) {
-    Plan p;
-    if (CONN8) {
-        p.l = start && cL;
-        p.m = start && cM && !sameLM;
-        p.r = cR && !sameMR;
-    } else {
-        p.l = false;
-        p.m = cM && (start || !sameLM);
-        p.r = false;
-    }
-    return p;
 }
 
 // ---------------------------------------------------------- LDS union-find
@@ -197,54 +174,91 @@ __device__ __forceinline__ void lds_union(uint32_t *par, uint32_t a, uint32_t b)
 
 // ------------------------------------------------------ global union-find
 
-// Find with path halving for the concurrent boundary phase.  The halving
-// write is an atomicMin, so it can only lower a parent to an ancestor.
-__device__ __forceinline__ uint32_t g_find(uint32_t *L, uint32_t x) {
+// Roots of a and b in the global forest, found together so that the loads
+// of both walks are in flight at once.  Path halving: a node whose parent
+// is not a root is pointed at its grandparent with an atomicMin, which can
+// only lower a parent to an ancestor.
+__device__ __forceinline__ void g_find2(uint32_t *L, uint32_t &a, uint32_t &b) {
+    bool ra = false, rb = false;
     while (true) {
-        const uint32_t p = g_ld(&L[x]) - 1u;
-        if (p >= x) return x;
-        const uint32_t gp = g_ld(&L[p]) - 1u;
-        if (gp >= p) return p;
-        g_min(&L[x], gp + 1u);
-        x = gp;
+        const uint32_t pa = ra ? a : g_ld(&L[a]) - 1u;
+        const uint32_t pb = rb ? b : g_ld(&L[b]) - 1u;
+        ra = ra || pa >= a;
+        rb = rb || pb >= b;
+        if (ra && rb) return;
+        const uint32_t ga = ra ? pa : g_ld(&L[pa]) - 1u;
+        const uint32_t gb = rb ? pb : g_ld(&L[pb]) - 1u;
+        if (!ra) {
+            if (ga >= pa) {
+                a = pa;
+                ra = true;
+            } else {
+                g_min(&L[a], ga + 1u);
+                a = ga;
+            }
+        }
+        if (!rb) {
+            if (gb >= pb) {
+                b = pb;
+                rb = true;
+            } else {
+                g_min(&L[b], gb + 1u);
+                b = gb;
+            }
+        }
+        if (ra && rb) return;
     }
 }
 
+// Link the trees of a and b, the larger root under the smaller (Sec. II-B).
+// When the atomicMin shows that b stopped being a root meanwhile, the value
+// it returns is b's new parent and the link is retried from there, so no
+// concurrent link is lost.
 __device__ __forceinline__ void g_union(uint32_t *L, uint32_t n, uint32_t a, uint32_t b) {
     if (a >= n || b >= n) return;
     while (true) {
-        a = g_find(L, a);
-        b = g_find(L, b);
+        g_find2(L, a, b);
         if (a == b) return;
         if (a > b) { const uint32_t t = a; a = b; b = t; }
-        const uint32_t old = g_min(&L[b], a + 1u);
-        if (old - 1u >= b) return;
-        b = old - 1u;
+        const uint32_t old = g_min(&L[b], a + 1u) - 1u;
+        if (old >= b) return;
+        b = old;
     }
 }
 
-// Keep, of all (a, b) merge requests a wavefront holds in two slots, only
-// the first occurrence of every distinct pair (lanes with b == kNone hold
-// none).  Along one tile edge most requests repeat the same two tile-local
-// roots, so this cuts the global unions to one per distinct pair.
-__device__ __forceinline__ void dedupe_pairs(uint32_t a, uint32_t b0, uint32_t b1, bool &keep0,
-                                             bool &keep1) {
+// Merge requests of one wavefront: every lane holds NS (a, b) slots (b ==
+// kNone: empty).  Along a tile edge most requests repeat the same pair of
+// tile-local roots, so the distinct pairs are collected first (one per
+// lane, at most 64 at a time) and then merged by all lanes concurrently.
+template <int NS>
+__device__ __forceinline__ void union_requests(uint32_t *L, uint32_t n, const uint32_t (&A)[NS],
+                                               const uint32_t (&B)[NS]) {
     const int lane = (int)(threadIdx.x & 63);
-    uint64_t pend0 = __ballot(b0 != kNone), pend1 = __ballot(b1 != kNone);
-    keep0 = false;
-    keep1 = false;
-    while (pend0 | pend1) {
-        const bool first = pend0 != 0;
-        const int lead = __builtin_ctzll(first ? pend0 : pend1);
-        const uint32_t A = (uint32_t)__builtin_amdgcn_readlane((int)a, lead);
-        const uint32_t B = (uint32_t)__builtin_amdgcn_readlane((int)(first ? b0 : b1), lead);
-        if (lane == lead) {
-            if (first) keep0 = true;
-            else keep1 = true;
+    uint64_t pend[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) pend[s] = __ballot(B[s] != kNone);
+    uint32_t ma = kNone, mb = kNone;
+    int cnt = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        while (pend[s]) {
+            const int lead = __builtin_ctzll(pend[s]);
+            const uint32_t PA = (uint32_t)__builtin_amdgcn_readlane((int)A[s], lead);
+            const uint32_t PB = (uint32_t)__builtin_amdgcn_readlane((int)B[s], lead);
+            if (lane == cnt) {
+                ma = PA;
+                mb = PB;
+            }
+#pragma unroll
+            for (int q = s; q < NS; ++q) pend[q] &= ~__ballot(A[q] == PA && B[q] == PB);
+            if (++cnt == 64) {
+                g_union(L, n, ma, mb);
+                ma = mb = kNone;
+                cnt = 0;
+            }
         }
-        pend0 &= ~__ballot(b0 != kNone && a == A && b0 == B);
-        pend1 &= ~__ballot(b1 != kNone && a == A && b1 == B);
     }
+    if (mb != kNone) g_union(L, n, ma, mb);
 }
 
 // Find for the link phase.  No link is made any more, so every root is
@@ -339,24 +353,28 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Which (lower run, upper run) pairs of two adjacent rows inside one tile are
-// merged, as lane masks over the lower row d with the upper row u: every pair
-// of runs that touch is taken exactly once, by the leftmost lower cell
-// adjacent to the upper run.  8-connectivity: PL = the upper run containing
-// column j-1 (only at a lower run start), PM = the upper run starting at j
-// (only at a lower run start whose above-left is empty), PR = the upper run
-// starting at j+1.  4-connectivity: PM = the upper run containing j, at the
-// lower run start or where the upper run starts.
+// Which (lower run, upper run) pairs of two adjacent lines are merged, as
+// lane masks over the lower line d with the upper line u: every pair of runs
+// that touch is taken exactly once, by the leftmost lower cell adjacent to
+// the upper run.  8-connectivity: PL = the upper run containing column j-1
+// (only at a lower run start), PM = the upper run starting at j (only at a
+// lower run start whose above-left is empty), PR = the upper run starting at
+// j+1.  4-connectivity: PM = the upper run containing j, at the lower run
+// start or where the upper run starts.  On a tile's top edge the upper line
+// continues into the neighbouring tiles: xl (bit 0 only) is set when the
+// cell above-left of column 0 is foreground, xr (bit 63 only) when the cell
+// above-right of column 63 is; inside a tile both are 0.
 struct PairMasks { uint64_t pl, pm, pr; };
 
 template <bool CONN8>
-__device__ __forceinline__ PairMasks pair_masks(uint64_t d, uint64_t u) {
+__device__ __forceinline__ PairMasks pair_masks(uint64_t d, uint64_t u, uint64_t xl = 0,
+                                                uint64_t xr = 0) {
     const uint64_t S = run_starts(d);
     PairMasks p;
     if (CONN8) {
-        p.pl = S & (u << 1);
+        p.pl = S & ((u << 1) | xl);
         p.pm = S & u & ~(u << 1);
-        p.pr = d & (u >> 1) & ~u;
+        p.pr = d & (((u >> 1) & ~u) | xr);
     } else {
         p.pl = 0;
         p.pm = d & u & (S | ~(u << 1));

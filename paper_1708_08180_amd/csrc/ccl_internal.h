@@ -16,11 +16,11 @@ bool config_supported(int th, int nw);
 // The three batch kernels of one configuration.  Each takes one BatchArgs
 // by value.  Grids: local merge and link one workgroup (block1 / block3
 // threads) per tile; boundary analysis one workgroup (block2 threads) per
-// segs_per_group edge segments.
+// tiles_per_group2 tiles.
 struct BatchKernels {
     const void *k1, *k2, *k3;
     unsigned block1, block2, block3;
-    unsigned segs_per_group;
+    unsigned tiles_per_group2;
 };
 bool batch_kernels(int th, int nw, int conn, BatchKernels *out);
 

@@ -7,17 +7,17 @@
 //                      workspace, and seeds labels[root] = root + 1 for roots
 //                      whose component touches a shared tile edge.
 //   boundary analysis  Sec. II-B (Kernel 2): union-find on tile-edge cells
-//                      only, one wavefront per tile edge; the only phase with
-//                      global atomics.
+//                      only, one wavefront per tile (its top and left
+//                      edges); the only phase with global atomics.
 //   link               Sec. II-C: reads each tile's row masks and run
 //                      records, resolves each edge-touching local root once
 //                      in the global forest and writes the dense output
 //                      labels (1 + root, 0 for background).
 //
-// The per-tile and per-edge bodies are device functions shared by the
-// single-image kernels (one workgroup per tile / per four edges) and the
-// batch kernels (the same bodies over one global numbering of the tiles and
-// edge segments of all images).
+// The per-tile bodies are device functions shared by the single-image
+// kernels (one workgroup per tile; four tiles per workgroup for the
+// boundary analysis) and the batch kernels (the same bodies over one global
+// numbering of the tiles of all images).
 
 #include "ccl_device.h"
 #include "ccl_internal.h"
@@ -160,67 +160,67 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH> 
 
 // ------------------------------------------------------ boundary analysis
 
-// One wavefront per tile edge.  Edge segments [0, nH) are the horizontal
-// edges (tile (tx, ty) against the tile above, ty >= 1), segments
-// [nH, nH + nV) the vertical edges (tile (tx, ty) against the tile on its
-// left, tx >= 1).  Horizontal edges also take the diagonal pairs that cross
-// a tile corner; vertical edges take only pairs inside one tile row, so every
-// adjacent foreground pair that crosses tiles is examined by exactly one edge.
+// One wavefront per tile: the tile's top edge against the tile above (64
+// lanes, one per column; it also takes the diagonal pairs that cross the
+// tile's upper corners) and its left edge against the tile on its left (TH
+// lanes, one per row; pairs inside one tile row only), so every adjacent
+// foreground pair that crosses tiles is examined by exactly one edge.  All
+// masks and edge-cell roots are loaded up front; the neighbours' roots come
+// from lane shifts.  Each lane holds up to four merge requests (two per
+// edge), which are deduplicated and merged together.
 template <int TH, bool CONN8>
-__device__ __forceinline__ void k2_segment(const ImgView &v, uint32_t seg, uint32_t nH) {
-    const int lane = lane_id();
+__device__ __forceinline__ void k2_tile(const ImgView &v, uint32_t t) {
     constexpr int RT = roots_per_tile(TH);
+    const int lane = lane_id();
     const uint32_t TX = (uint32_t)v.tilesX;
-    uint32_t a = kNone, b0 = kNone, b1 = kNone;
-    if (seg < nH) {
-        const uint32_t tx = seg % TX, ty = seg / TX + 1u;
-        const uint32_t tl = ty * TX + tx, tu = tl - TX;
-        const uint64_t d = v.masks[(size_t)tl * 4 + kMaskTop];
-        const uint64_t u = v.masks[(size_t)tu * 4 + kMaskBottom];
-        const bool hasL = tx > 0, hasR = tx + 1u < TX;
-        const uint64_t uL = hasL ? v.masks[(size_t)(tu - 1) * 4 + kMaskBottom] : 0ull;
-        const uint64_t uR = hasR ? v.masks[(size_t)(tu + 1) * 4 + kMaskBottom] : 0ull;
-        if (bit(d, lane)) {
-            const bool cL = lane > 0 ? bit(u, lane - 1) : (int)(uL >> 63);
-            const bool cM = bit(u, lane);
-            const bool cR = lane < 63 ? bit(u, lane + 1) : (int)(uR & 1ull);
-            const bool start = !(lane > 0 && bit(d, lane - 1));
-            const Plan p = plan_pairs<CONN8>(start, cL, cM, cR, lane > 0 && cL && cM,
-                                             lane < 63 && cM && cR);
-            const uint32_t *ru = v.roots + (size_t)tu * RT + roots_bottom(TH);
-            if (p.l || p.m || p.r) a = v.roots[(size_t)tl * RT + roots_top(TH) + lane];
-            // At lane 0 the above-left cell lies in the tile to the left, so
-            // the left and middle requests can both be needed; otherwise at
-            // most one of them is, and it never coexists with the right one
-            // when both left and middle are set.
-            if (p.l) b0 = lane > 0 ? ru[lane - 1] : ru[-RT + 63];
-            else if (p.m) b0 = ru[lane];
-            if (p.r) b1 = lane < 63 ? ru[lane + 1] : ru[RT];
-            else if (p.l && p.m) b1 = ru[lane];
+    const uint32_t tx = t % TX, ty = t / TX;
+    const bool hasT = ty > 0, hasL = tx > 0, hasR = tx + 1u < TX;
+    const uint64_t *mk = v.masks;
+    const uint32_t *rts = v.roots;
+    uint64_t dT = 0, uT = 0, xl = 0, xr = 0, dL = 0, uL = 0;
+    uint32_t aT = kNone, rT = kNone, eTL = kNone, eTR = kNone, aL = kNone, rL = kNone;
+    if (hasT) {
+        const uint32_t tu = t - TX;
+        dT = mk[(size_t)t * 4 + kMaskTop];
+        uT = mk[(size_t)tu * 4 + kMaskBottom];
+        if (hasL) {
+            xl = mk[(size_t)(tu - 1u) * 4 + kMaskBottom] >> 63;
+            eTL = rts[(size_t)(tu - 1u) * RT + roots_bottom(TH) + 63];
         }
-    } else {
-        const uint32_t s = seg - nH;
-        const uint32_t tx = s % (TX - 1u) + 1u, ty = s / (TX - 1u);
-        const uint32_t tr = ty * TX + tx, tlft = tr - 1u;
-        const uint64_t d = v.masks[(size_t)tr * 4 + kMaskLeft];
-        const uint64_t u = v.masks[(size_t)tlft * 4 + kMaskRight];
-        if (lane < TH && bit(d, lane)) {
-            const bool cL = lane > 0 && bit(u, lane - 1);
-            const bool cM = bit(u, lane);
-            const bool cR = lane + 1 < TH && bit(u, lane + 1);
-            const bool start = !(lane > 0 && bit(d, lane - 1));
-            const Plan p = plan_pairs<CONN8>(start, cL, cM, cR, cL && cM, cM && cR);
-            const uint32_t *ru = v.roots + (size_t)tlft * RT + roots_right(TH);
-            if (p.l || p.m || p.r) a = v.roots[(size_t)tr * RT + roots_left(TH) + lane];
-            if (p.l) b0 = ru[lane - 1];
-            else if (p.m) b0 = ru[lane];
-            if (p.r) b1 = ru[lane + 1];
+        if (hasR) {
+            xr = (mk[(size_t)(tu + 1u) * 4 + kMaskBottom] & 1ull) << 63;
+            eTR = rts[(size_t)(tu + 1u) * RT + roots_bottom(TH)];
+        }
+        aT = rts[(size_t)t * RT + roots_top(TH) + lane];
+        rT = rts[(size_t)tu * RT + roots_bottom(TH) + lane];
+    }
+    if (hasL) {
+        dL = mk[(size_t)t * 4 + kMaskLeft];
+        uL = mk[(size_t)(t - 1u) * 4 + kMaskRight];
+        if (lane < TH) {
+            aL = rts[(size_t)t * RT + roots_left(TH) + lane];
+            rL = rts[(size_t)(t - 1u) * RT + roots_right(TH) + lane];
         }
     }
-    bool keep0, keep1;
-    dedupe_pairs(a, b0, b1, keep0, keep1);
-    if (keep0) g_union(v.labels, v.n, a, b0);
-    if (keep1) g_union(v.labels, v.n, a, b1);
+    // roots of the cells above-left / above-right (left edge: above / below)
+    const uint32_t bTl = from_left(rT, eTL), bTr = from_right(rT, eTR);
+    const uint32_t bLl = from_left(rL, kNone), bLr = from_right(rL, kNone);
+    uint32_t A[4], B[4];
+    {
+        const PairMasks p = pair_masks<CONN8>(dT, uT, xl, xr);
+        // at lane 0 the above-left cell lies in the tile to the left, so
+        // PL and PM can both hold there; elsewhere they exclude each other
+        B[0] = lane_in(p.pl) ? bTl : (lane_in(p.pm) ? rT : kNone);
+        B[1] = lane_in(p.pr) ? bTr : (lane_in(p.pl & p.pm) ? rT : kNone);
+        A[0] = A[1] = aT;
+    }
+    {
+        const PairMasks p = pair_masks<CONN8>(dL, uL);
+        B[2] = lane_in(p.pl) ? bLl : (lane_in(p.pm) ? rL : kNone);
+        B[3] = lane_in(p.pr) ? bLr : kNone;
+        A[2] = A[3] = aL;
+    }
+    union_requests<4>(v.labels, v.n, A, B);
 }
 
 // ----------------------------------------------------------------- link
@@ -286,10 +286,10 @@ __global__ void __launch_bounds__(NW * 64) k1_local_merge(ImgView v) {
 }
 
 template <int TH, bool CONN8>
-__global__ void __launch_bounds__(256) k2_boundary(ImgView v, uint32_t nH, uint32_t nV) {
-    const uint32_t seg = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (seg >= nH + nV) return;  // wave-uniform
-    k2_segment<TH, CONN8>(v, seg, nH);
+__global__ void __launch_bounds__(256) k2_boundary(ImgView v, uint32_t tiles) {
+    const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4u + (threadIdx.x >> 6)));
+    if (t >= tiles) return;  // wave-uniform
+    k2_tile<TH, CONN8>(v, t);
 }
 
 template <int TH, int NW>
@@ -300,20 +300,20 @@ __global__ void __launch_bounds__(NW * 64) k3_link(ImgView v) {
 
 // ------------------------------------------------------------ batch kernels
 
-// Image that owns global item g (a tile or an edge segment): the last image
-// whose base is <= g, i.e. the number of bases <= g minus one.  Images with
-// no edge segments share their seg_base with the next image, and the count
-// then lands on the last of them, the one that owns the segment.  Each lane
-// compares one base per 64 images.
-__device__ __forceinline__ uint32_t batch_image_of(const uint32_t *base, uint32_t n, uint32_t g) {
+// Image that owns global tile g: the last image whose tile_base is <= g,
+// i.e. the number of bases <= g minus one.  First among the coarse bases
+// (every 64th image), then among the 64 images of that group; each lane
+// compares one base.
+__device__ __forceinline__ uint32_t batch_image_of(const BatchArgs &a, uint32_t g) {
     const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t nc = (a.n + 63u) >> 6;
     uint32_t cnt = 0;
-#pragma unroll 4
-    for (uint32_t j = 0; j < n; j += 64) {
+    for (uint32_t j = 0; j < nc; j += 64) {
         const uint32_t k = j + lane;
-        cnt += (uint32_t)__popcll(__ballot(k < n && base[k] <= g));
+        cnt += (uint32_t)__popcll(__ballot(k < nc && a.coarse[k] <= g));
     }
-    return cnt - 1u;
+    const uint32_t k = ((cnt - 1u) << 6) + lane;
+    return ((cnt - 1u) << 6) + (uint32_t)__popcll(__ballot(k < a.n && a.tile_base[k] <= g)) - 1u;
 }
 
 template <int TH>
@@ -335,27 +335,27 @@ __device__ __forceinline__ ImgView batch_view(const BatchImage &b, const BatchWs
     return v;
 }
 
-// The batch kernels are the single-image ones over the global tile (edge
-// segment) numbering of all images: one workgroup per tile for the local
-// merge and the link, four edge segments per workgroup for the boundary
-// analysis.  The host sizes the grids for every call.
+// The batch kernels are the single-image ones over one global numbering of
+// the tiles of all images: one workgroup per tile for the local merge and
+// the link, four tiles per workgroup for the boundary analysis.  The host
+// sizes the grids for every call.
 template <int TH, int NW, bool CONN8>
 __global__ void __launch_bounds__(NW * 64) k1_batch(BatchArgs a) {
     __shared__ K1Lds<TH> sh;
     const uint32_t g = xcd_remap(blockIdx.x, gridDim.x);
     if (g >= a.tiles) return;  // workgroup-uniform
-    const uint32_t i = batch_image_of(a.tile_base, a.n, g);
+    const uint32_t i = batch_image_of(a, g);
+    if (threadIdx.x == 0) a.w.tile_img[g] = i;
     const BatchImage &d = a.descs[i];
     k1_tile<TH, NW, CONN8>(batch_view<TH>(d, a.w), g - d.tile_base, sh);
 }
 
 template <int TH, bool CONN8>
 __global__ void __launch_bounds__(256) k2_batch(BatchArgs a) {
-    const uint32_t s = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (s >= a.segs) return;  // wave-uniform
-    const uint32_t i = batch_image_of(a.seg_base, a.n, s);
-    const BatchImage &d = a.descs[i];
-    k2_segment<TH, CONN8>(batch_view<TH>(d, a.w), s - d.seg_base, d.nH);
+    const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4u + (threadIdx.x >> 6)));
+    if (g >= a.tiles) return;  // wave-uniform
+    const BatchImage &d = a.descs[a.w.tile_img[g]];
+    k2_tile<TH, CONN8>(batch_view<TH>(d, a.w), g - d.tile_base);
 }
 
 template <int TH, int NW>
@@ -363,26 +363,31 @@ __global__ void __launch_bounds__(NW * 64) k3_batch(BatchArgs a) {
     __shared__ uint32_t fin[TH * kTileW];
     const uint32_t g = xcd_remap(blockIdx.x, gridDim.x);
     if (g >= a.tiles) return;  // workgroup-uniform
-    const uint32_t i = batch_image_of(a.tile_base, a.n, g);
-    const BatchImage &d = a.descs[i];
+    const BatchImage &d = a.descs[a.w.tile_img[g]];
     k3_tile<TH, NW>(batch_view<TH>(d, a.w), g - d.tile_base, fin);
 }
 
 // ---------------------------------------------------------------- launchers
 
+// Waves per workgroup of the link kernel: 16 rows per wave whatever the
+// local merge uses (measured best at 32 and 64 rows per tile).
+template <int TH>
+constexpr int link_waves() {
+    return TH / 16;
+}
+
 template <int TH, int NW, bool CONN8>
 static hipError_t launch_plain_t(const ImgView &v, hipStream_t stream, hipEvent_t *ev) {
     const uint32_t tiles = (uint32_t)v.tilesX * (uint32_t)v.tilesY;
-    const uint32_t nH = (uint32_t)v.tilesX * (uint32_t)(v.tilesY - 1);
-    const uint32_t nV = (uint32_t)(v.tilesX - 1) * (uint32_t)v.tilesY;
     if (ev) (void)hipEventRecord(ev[0], stream);
     hipLaunchKernelGGL((k1_local_merge<TH, NW, CONN8>), dim3(tiles), dim3(NW * 64), 0, stream, v);
     if (ev) (void)hipEventRecord(ev[1], stream);
-    if (nH + nV > 0)
-        hipLaunchKernelGGL((k2_boundary<TH, CONN8>), dim3((nH + nV + 3) / 4), dim3(256), 0, stream,
-                           v, nH, nV);
+    if (tiles > 1)
+        hipLaunchKernelGGL((k2_boundary<TH, CONN8>), dim3((tiles + 3) / 4), dim3(256), 0, stream,
+                           v, tiles);
     if (ev) (void)hipEventRecord(ev[2], stream);
-    hipLaunchKernelGGL((k3_link<TH, NW>), dim3(tiles), dim3(NW * 64), 0, stream, v);
+    constexpr int NW3 = link_waves<TH>();
+    hipLaunchKernelGGL((k3_link<TH, NW3>), dim3(tiles), dim3(NW3 * 64), 0, stream, v);
     if (ev) (void)hipEventRecord(ev[3], stream);
     return hipGetLastError();
 }
@@ -391,10 +396,11 @@ template <int TH, int NW, bool CONN8>
 static void batch_kernels_t(BatchKernels *k) {
     k->k1 = (const void *)k1_batch<TH, NW, CONN8>;
     k->k2 = (const void *)k2_batch<TH, CONN8>;
-    k->k3 = (const void *)k3_batch<TH, NW>;
-    k->block1 = k->block3 = NW * 64;
+    k->k3 = (const void *)k3_batch<TH, link_waves<TH>()>;
+    k->block1 = NW * 64;
+    k->block3 = link_waves<TH>() * 64;
     k->block2 = 256;
-    k->segs_per_group = 4;
+    k->tiles_per_group2 = 4;
 }
 
 bool config_supported(int th, int nw) {
