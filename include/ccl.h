@@ -89,7 +89,7 @@ int ccl_version(void);
  *         written as described at the top of this file.
  * stream  hipStream_t (void*), NULL for the null stream.
  *
- * Scratch: a per-(device, stream) workspace (about 1.4 bytes per pixel for
+ * Scratch: a per-(device, stream) workspace (about 1.5 bytes per pixel for
  * the default tiles) is allocated on first use and grown
  * when a larger image arrives on the same stream (growth synchronizes that
  * stream before freeing the old buffer); ccl_shutdown releases it.  Two

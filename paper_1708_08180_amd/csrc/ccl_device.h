@@ -21,10 +21,14 @@
 //                   masks (boundary analysis)
 //   roots[...]      global raster index of the tile-local root of every cell
 //                   on those four edges (boundary analysis)
-//   rowmask[TH]     the 64-bit foreground mask of every tile row (link)
+//   rowmask[2*TH]   the 64-bit foreground mask of every tile row, then per
+//                   row the mask of the local root pixels whose component
+//                   touches a shared tile edge (link)
 //   slots[TH][32]   per row, one 16-bit record per run in left-to-right
-//                   order: the run's tile-local root, with kSlotFlag set when
-//                   that root's component touches a shared tile edge (link)
+//                   order: the tile-local pixel index of the run's local
+//                   root (link)
+// Every root of an edge-touching component is also seeded in the forest,
+// labels[root] = root + 1, before the boundary analysis runs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,16 +36,12 @@
 
 namespace ccl {
 
-constexpr int kTileW = 64;            // tile width == wavefront width
-constexpr uint32_t kFlag = 0x80000000u;  // "touches a shared tile edge" mark in LDS parents
-constexpr uint32_t kIdx = 0x7FFFFFFFu;
-constexpr uint32_t kNone = 0xFFFFFFFFu;   // "no node"
+constexpr int kTileW = 64;               // tile width == wavefront width
+constexpr uint32_t kNone = 0xFFFFFFFFu;  // "no node"
 
 enum { kMaskTop = 0, kMaskBottom = 1, kMaskLeft = 2, kMaskRight = 3 };
 
-// Per-run record handed from the local merge to the link phase.
-constexpr uint16_t kSlotFlag = 0x8000u;  // the component touches a shared tile edge
-constexpr int kSlotsPerRow = 32;         // a 64-pixel row has at most 32 runs
+constexpr int kSlotsPerRow = 32;  // a 64-pixel row has at most 32 runs
 
 __host__ __device__ constexpr int roots_per_tile(int th) { return 2 * kTileW + 2 * th; }
 __host__ __device__ constexpr int roots_top(int) { return 0; }
@@ -55,7 +55,7 @@ struct ImgView {
     uint32_t *labels;
     uint64_t *masks;    // [tiles][4]
     uint32_t *roots;    // [tiles][roots_per_tile(TH)]
-    uint64_t *rowmask;  // [tiles][TH]
+    uint64_t *rowmask;  // [tiles][2*TH]: row masks, then edge-root masks
     uint16_t *slots;    // [tiles][TH][kSlotsPerRow]
     int64_t pitch;
     int32_t H, W;
@@ -386,16 +386,13 @@ __device__ __forceinline__ PairMasks pair_masks(uint64_t d, uint64_t u, uint64_t
 // Sweep of one wavefront's band of rows, top to bottom (Sec. II-A-2/3).
 // `ra` carries, per lane, the root node of the pixel above (kNone for
 // background), so the roots a run touches come from neighbouring lanes'
-// registers.  A run's parent becomes the smallest of those roots (LDS
-// atomicMin on its node); every other root it touches is joined to that one
-// by a real union, which is rare.  Only after a row that had one are the
-// row's roots re-resolved, so `ra` always holds true roots.
-// rinfo[r] (written here, one byte per row): number of runs in bits 0..5,
-// bit 6 = the row's first run starts at column 0, bit 7 = its last run ends
-// at column 63.
+// registers.  A run's parent becomes the smallest of those roots (one LDS
+// atomicMin per lane on its node); every other root it touches is joined
+// to that one by a real union, which is rare.  Only after a row that had one
+// are the row's roots re-resolved, so `ra` always holds true roots.
 template <int TH, int RPW, bool CONN8>
-__device__ __forceinline__ void sweep_band(uint32_t *par, uint8_t *col, uint8_t *rinfo,
-                                           const uint64_t *msk, int wave, int lane) {
+__device__ __forceinline__ void sweep_band(uint32_t *par, uint8_t *col, const uint64_t *msk,
+                                           int wave, int lane) {
     uint32_t ra = kNone;
     uint64_t u = 0;
     uint64_t m[RPW];
@@ -408,28 +405,27 @@ __device__ __forceinline__ void sweep_band(uint32_t *par, uint8_t *col, uint8_t 
         const uint64_t S = run_starts(d);
         const bool fg = lane_in(d), isS = lane_in(S);
         const uint32_t node = (uint32_t)(r * kSlotsPerRow) + bits_below(S) - (isS ? 0u : 1u);
+        uint32_t *pn = &par[node];
         if (isS) {
-            lds_st(&par[node], node);
+            lds_st(pn, node);
             col[node] = (uint8_t)lane;
         }
-        if (lane == 0)
-            rinfo[r] = (uint8_t)(__popcll(S) | ((d & 1ull) ? 0x40 : 0) | ((d >> 63) ? 0x80 : 0));
         uint32_t md = fg ? node : kNone;
         if (k > 0) {
             const PairMasks p = pair_masks<CONN8>(d, u);
             const uint32_t rL = from_left(ra, kNone), rR = from_right(ra, kNone);
             const uint32_t t0 = lane_in(p.pl) ? rL : (lane_in(p.pm) ? ra : kNone);
             const uint32_t t1 = lane_in(p.pr) ? rR : kNone;
-            if (t0 != kNone) atomicMin(&par[node], t0);
-            if (t1 != kNone) atomicMin(&par[node], t1);
-            if (fg) md = lds_ld(&par[node]);
+            const uint32_t tm = t0 < t1 ? t0 : t1;
+            if (tm != kNone) atomicMin(pn, tm);
+            if (fg) md = lds_ld(pn);
             const bool n0 = t0 != kNone && t0 != md;
             const bool n1 = t1 != kNone && t1 != md;
             if (__ballot(n0 || n1)) {
                 if (n0) lds_union(par, t0, md);
                 if (n1) lds_union(par, t1, md);
                 if (fg) md = lds_root(par, md);
-                if (isS) lds_st(&par[node], md);
+                if (isS) lds_st(pn, md);
             }
         }
         ra = md;

@@ -29,7 +29,8 @@ bool batch_kernels(int th, int nw, int conn, BatchKernels *out);
 hipError_t launch_plain(const ImgView &v, int th, int nw, int conn, hipStream_t s,
                         hipEvent_t *ev = nullptr);
 
-// Workspace layout for one image: edge masks, edge-cell roots, row masks, run slots.
+// Workspace layout for one image: edge masks, edge-cell roots, row masks
+// (row foreground and edge-root masks), run slots.
 struct WsLayout {
     size_t tiles;
     size_t mask_bytes;
@@ -48,7 +49,7 @@ inline WsLayout ws_layout(int H, int W, int th) {
     l.tiles = tx * ty;
     l.mask_bytes = align_up(l.tiles * 4 * sizeof(uint64_t), 256);
     l.root_bytes = align_up(l.tiles * (size_t)roots_per_tile(th) * sizeof(uint32_t), 256);
-    l.rowmask_bytes = align_up(l.tiles * (size_t)th * sizeof(uint64_t), 256);
+    l.rowmask_bytes = align_up(l.tiles * 2 * (size_t)th * sizeof(uint64_t), 256);
     l.slot_bytes = align_up(l.tiles * (size_t)th * kSlotsPerRow * sizeof(uint16_t), 256);
     l.total = l.mask_bytes + l.root_bytes + l.rowmask_bytes + l.slot_bytes;
     return l;

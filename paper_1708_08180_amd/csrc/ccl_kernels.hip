@@ -42,6 +42,7 @@ struct K1Lds {
     uint32_t par[TH * kSlotsPerRow];  // run-indexed parents
     uint8_t col[TH * kSlotsPerRow];   // first column of every run
     uint64_t msk[TH];                 // row masks
+    uint64_t flg[TH];                 // per row: local roots of edge-touching components
     uint8_t rinfo[TH];                // runs per row | first run at column 0 | last at 63
 };
 
@@ -58,10 +59,13 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH> 
     uint32_t *par = sh.par;
     uint8_t *col = sh.col;
     uint64_t *msk = sh.msk;
+    uint64_t *flg = sh.flg;
     uint8_t *rinfo = sh.rinfo;
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t TX = (uint32_t)v.tilesX;
     const int tx = (int)(t % TX), ty = (int)(t / TX);
+    const bool hasUp = ty > 0, hasDown = ty + 1 < v.tilesY;
+    const bool hasLeft = tx > 0, hasRight = tx + 1 < v.tilesX;
 
     // row masks into LDS (16 pixels per chunk)
 #pragma unroll
@@ -70,20 +74,27 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH> 
         if (c < CH)
             ((uint16_t *)msk)[c] = (uint16_t)nonzero_bytes16(load_chunk(v, tx, ty, TH, c >> 2, c & 3));
     }
+    if (tid < TH) flg[tid] = 0ull;
     __syncthreads();
-    sweep_band<TH, RPW, CONN8>(par, col, rinfo, msk, wave, lane);
+    // per-row run counts and edge bits, one row per thread (read after the
+    // barriers that follow the sweep)
+    if (tid < TH) {
+        const uint64_t d = msk[tid];
+        rinfo[tid] = (uint8_t)(__popcll(run_starts(d)) | ((d & 1ull) ? 0x40 : 0) |
+                               ((d >> 63) ? 0x80 : 0));
+    }
+    sweep_band<TH, RPW, CONN8>(par, col, msk, wave, lane);
     if (NW > 1) {
         __syncthreads();
         if (wave > 0) merge_seam<CONN8>(par, msk, wave * RPW);
     }
     __syncthreads();
 
-    // node-parallel finish.  Pass 1: every node finds its root (read-only
-    // walk) and its owner alone stores it, so par[n] is the root afterwards;
-    // roots are never stored to, so the edge marks ORed into them survive
-    // (a marked root still reads as a root: its value is >= its index).
-    const bool hasUp = ty > 0, hasDown = ty + 1 < v.tilesY;
-    const bool hasLeft = tx > 0, hasRight = tx + 1 < v.tilesX;
+    // node-parallel finish: every node finds its root (read-only walk) and
+    // its owner alone stores it, so par[n] is the root afterwards; the run's
+    // record (the root's tile-local pixel) goes out, and edge runs mark
+    // their root pixel in the edge-root masks.
+    uint16_t *sl = v.slots + (size_t)t * TH * kSlotsPerRow;
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
         const int n = tid + i * NT;
@@ -94,60 +105,53 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH> 
         if (k >= runs) continue;
         const uint32_t root = lds_root(par, (uint32_t)n);
         if (root != (uint32_t)n) lds_st(&par[n], root);
+        const uint32_t rc = col[root];
+        sl[n] = (uint16_t)((root >> 5) * kTileW + rc);
         const bool edge = (r == 0 && hasUp) || (r == TH - 1 && hasDown) ||
                           (k == 0 && (info & 0x40u) && hasLeft) ||
                           (k == runs - 1 && (info & 0x80u) && hasRight);
-        if (edge) atomicOr(&par[root], kFlag);
+        if (edge) atomicOr((unsigned long long *)&flg[root >> 5], 1ull << rc);
     }
     __syncthreads();
-    uint16_t *sl = v.slots + (size_t)t * TH * kSlotsPerRow;
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-        const int n = tid + i * NT;
-        if (n >= NODES) break;
-        if ((n & 31) >= (int)(rinfo[n >> 5] & 63u)) continue;
-        const uint32_t root = lds_ld(&par[n]) & kIdx;
-        const uint32_t flag = lds_ld(&par[root]) & kFlag;
-        const uint32_t rpix = (root >> 5) * kTileW + col[root];
-        sl[n] = (uint16_t)(rpix | (flag ? kSlotFlag : 0u));
-        if (root == (uint32_t)n && flag) {
-            const uint32_t g = global_index(v, tx, ty, TH, rpix);
-            v.labels[g] = g + 1u;
-        }
+    if (tid < TH) {
+        v.rowmask[(size_t)t * 2 * TH + tid] = msk[tid];
+        v.rowmask[(size_t)t * 2 * TH + TH + tid] = flg[tid];
     }
-    if (tid < TH) v.rowmask[(size_t)t * TH + tid] = msk[tid];
-    // edge masks and edge-cell roots for the boundary analysis
+    // edge masks and edge-cell roots for the boundary analysis; every such
+    // root is seeded in the forest (lanes of one component store the same
+    // word)
     if (wave == 0) {
         uint64_t *mk = v.masks + (size_t)t * 4;
         uint32_t *rt = v.roots + (size_t)t * roots_per_tile(TH);
         const uint64_t mTop = uniform64(msk[0]);
         const uint64_t mBot = uniform64(msk[TH - 1]);
-        // root pixel (tile-local index) of run node n
-        auto root_pix = [&](uint32_t n) {
-            const uint32_t root = lds_ld(&par[n]) & kIdx;
-            return (root >> 5) * kTileW + col[root];
+        // global index of the root pixel of run node n
+        auto root_g = [&](uint32_t n) {
+            const uint32_t root = lds_ld(&par[n]);
+            return global_index(v, tx, ty, TH, (root >> 5) * kTileW + col[root]);
+        };
+        auto put = [&](uint32_t *dst, uint32_t g) {
+            *dst = g;
+            v.labels[g] = g + 1u;
         };
         if (hasUp && lane_in(mTop)) {
             const uint64_t S = run_starts(mTop);
             const uint32_t n = bits_below(S) - (lane_in(S) ? 0u : 1u);
-            rt[roots_top(TH) + lane] = global_index(v, tx, ty, TH, root_pix(n));
+            put(&rt[roots_top(TH) + lane], root_g(n));
         }
         if (hasDown && lane_in(mBot)) {
             const uint64_t S = run_starts(mBot);
             const uint32_t n = (uint32_t)((TH - 1) * kSlotsPerRow) + bits_below(S) -
                                (lane_in(S) ? 0u : 1u);
-            rt[roots_bottom(TH) + lane] = global_index(v, tx, ty, TH, root_pix(n));
+            put(&rt[roots_bottom(TH) + lane], root_g(n));
         }
         const uint64_t mr = lane < TH ? msk[lane] : 0ull;
         const bool lb = (mr & 1ull) != 0, rb = (mr >> 63) != 0;
         const uint64_t mLeft = __ballot(lb), mRight = __ballot(rb);
-        if (hasLeft && lb)
-            rt[roots_left(TH) + lane] =
-                global_index(v, tx, ty, TH, root_pix((uint32_t)(lane * kSlotsPerRow)));
+        if (hasLeft && lb) put(&rt[roots_left(TH) + lane], root_g((uint32_t)(lane * kSlotsPerRow)));
         if (hasRight && rb)
-            rt[roots_right(TH) + lane] = global_index(
-                v, tx, ty, TH,
-                root_pix((uint32_t)(lane * kSlotsPerRow + __popcll(run_starts(mr)) - 1)));
+            put(&rt[roots_right(TH) + lane],
+                root_g((uint32_t)(lane * kSlotsPerRow + __popcll(run_starts(mr)) - 1)));
         if (lane == 0) {
             mk[kMaskTop] = mTop;
             mk[kMaskBottom] = mBot;
@@ -226,53 +230,60 @@ __device__ __forceinline__ void k2_tile(const ImgView &v, uint32_t t) {
 // ----------------------------------------------------------------- link
 
 // Link body for tile t (Sec. II-C): the local merge left the tile's row
-// masks and, per run, its tile-local root with an edge flag.  Each flagged
-// local root is resolved once in the global forest (and, being rewritten
-// with its final value, compressed for the tiles that still walk through
-// it); unflagged roots are already final.  Output rows are full 256-byte
-// lines.  Ends after a workgroup barrier.
+// masks, the masks of its local roots whose components touch a shared tile
+// edge, and per run its tile-local root pixel.  Every
+// local root pixel first puts its final label - 1 into fin[]: flagged roots
+// are resolved once in the global forest (and, being rewritten with their
+// final value, compressed for the tiles that still walk through them),
+// unflagged roots are already final.  Then every pixel reads its root's
+// entry; output rows are full 256-byte lines.  Ends after a workgroup
+// barrier.
 template <int TH, int NW>
 __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *fin) {
     constexpr int RPW = TH / NW;
-    const int tx = (int)(t % (uint32_t)v.tilesX), ty = (int)(t / (uint32_t)v.tilesX);
+    const uint32_t TX = (uint32_t)v.tilesX;
+    const uint32_t tx = t % TX, ty = t / TX;
     const int lane = lane_id();
-    const int wave = (int)(threadIdx.x >> 6);
-    const uint64_t *rm = v.rowmask + (size_t)t * TH;
-    const uint16_t *sl = v.slots + (size_t)t * TH * kSlotsPerRow;
-    uint64_t m[RPW];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t W = (uint32_t)v.W;
+    const uint64_t *rm = v.rowmask + (size_t)t * 2 * TH + wave * RPW;
+    const uint16_t *sl = v.slots + (size_t)t * TH * kSlotsPerRow + wave * RPW * kSlotsPerRow;
+    // global index of the tile's pixel (0, 0); every label fits in 32 bits
+    const uint32_t origin = ty * (uint32_t)TH * W + tx * (uint32_t)kTileW;
+    uint64_t m[RPW], f[RPW];
     uint32_t rec[RPW];
 #pragma unroll
-    for (int k = 0; k < RPW; ++k) m[k] = uniform64(rm[wave * RPW + k]);
+    for (int k = 0; k < RPW; ++k) {
+        m[k] = uniform64(rm[k]);
+        f[k] = uniform64(rm[TH + k]);
+    }
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
-        const int r = wave * RPW + k;
-        rec[k] = kNone;
-        if (lane_in(m[k])) {
-            const uint64_t S = run_starts(m[k]);
-            const uint32_t rank = bits_below(S) - (lane_in(S) ? 0u : 1u);
-            rec[k] = sl[r * kSlotsPerRow + rank];
-        }
+        // run of this lane (rank among the row's run starts at or below it;
+        // background lanes read some slot of the row and discard it)
+        const uint64_t S = run_starts(m[k]);
+        const uint32_t below = bits_below(S) + (lane_in(S) ? 1u : 0u);
+        const uint32_t rank = below ? below - 1u : 0u;
+        const uint32_t r = sl[k * kSlotsPerRow + rank];
+        rec[k] = lane_in(m[k]) ? r : kNone;
     }
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
         const uint32_t l = (uint32_t)((wave * RPW + k) * kTileW + lane);
-        if (rec[k] != kNone && (rec[k] & kSlotFlag) && (rec[k] & ~(uint32_t)kSlotFlag) == l)
-            fin[l] = g_find_final(v.labels, global_index(v, tx, ty, TH, l));
+        if (rec[k] == l) {
+            const uint32_t g = origin + (l >> 6) * W + (l & 63u);
+            fin[l] = lane_in(f[k]) ? g_find_final(v.labels, g) : g;
+        }
     }
     __syncthreads();
-    const int x = tx * kTileW + lane;
-    if (x < v.W) {
+    const uint32_t x = tx * (uint32_t)kTileW + (uint32_t)lane;
+    const uint32_t y0 = ty * (uint32_t)TH + (uint32_t)(wave * RPW);
+    uint32_t *out = v.labels + origin + (uint32_t)(wave * RPW) * W + (uint32_t)lane;
+    const bool full = (tx + 1u) * kTileW <= W && y0 + RPW <= (uint32_t)v.H;
 #pragma unroll
-        for (int k = 0; k < RPW; ++k) {
-            const int y = ty * TH + wave * RPW + k;
-            if (y >= v.H) break;
-            uint32_t out = 0u;
-            if (rec[k] != kNone) {
-                const uint32_t root = rec[k] & ~(uint32_t)kSlotFlag;
-                out = ((rec[k] & kSlotFlag) ? fin[root] : global_index(v, tx, ty, TH, root)) + 1u;
-            }
-            v.labels[(size_t)y * (size_t)v.W + (size_t)x] = out;
-        }
+    for (int k = 0; k < RPW; ++k) {
+        const uint32_t val = rec[k] != kNone ? fin[rec[k] & (TH * kTileW - 1)] + 1u : 0u;
+        if (full || (x < W && y0 + k < (uint32_t)v.H)) out[(size_t)k * W] = val;
     }
     __syncthreads();
 }
@@ -323,7 +334,7 @@ __device__ __forceinline__ ImgView batch_view(const BatchImage &b, const BatchWs
     v.labels = b.labels;
     v.masks = w.masks + (size_t)b.tile_base * 4;
     v.roots = w.roots + (size_t)b.tile_base * roots_per_tile(TH);
-    v.rowmask = w.rowmask + (size_t)b.tile_base * TH;
+    v.rowmask = w.rowmask + (size_t)b.tile_base * 2 * TH;
     v.slots = w.slots + (size_t)b.tile_base * TH * kSlotsPerRow;
     v.pitch = b.pitch;
     v.H = b.H;
