@@ -158,7 +158,8 @@ typedef struct ccl_image_desc {
  * max_pixels  most pixels per call, summed over images (>= 1); the tile
  *             workspace is sized for it with room for partial tiles.
  * cfg         tile configuration for every call ({0,0} = the library's
- *             choice for an image of max_pixels / max_images pixels).
+ *             choice for one image of max_pixels pixels: a call's grid
+ *             covers the tiles of all its images).
  * use_graph   nonzero: build one three-node hipGraph per connectivity and
  *             replay it; when a call's grids or arguments differ from the
  *             previous call's, the nodes are updated first (after waiting
@@ -268,7 +269,9 @@ int ccl_server_destroy(ccl_server *s);
  *
  * The tile configuration of ccl_label_2d is taken from a process-wide table
  * keyed by (size class = floor(log2(H*W)), connectivity); entries come from
- * ccl_autotune or ccl_tuning_load, misses use the built-in default. */
+ * ccl_autotune or ccl_tuning_load, misses use the built-in default:
+ * tile_h 32 with 8 wavefronts below 2^22 pixels, tile_h 64 with 4 from
+ * there up. */
 
 /* Time every supported tile configuration on the given image (device
  * buffers as in ccl_label_2d; `labels` is overwritten), `reps` calls each,

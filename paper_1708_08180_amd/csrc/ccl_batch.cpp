@@ -118,11 +118,12 @@ int ccl_ctx_create(ccl_ctx **out, const ccl_ctx_opts *opts) {
         delete c;
         return fail_hip(e);
     }
-    // default tiles: the choice for an average image, seen as a 1-row image of
-    // that many pixels (only the pixel count selects the size class)
-    const int64_t avg = opts->max_pixels / opts->max_images;
-    const int avg_w = (int)(avg < 1 ? 1 : (avg > 0x7fffffff ? 0x7fffffff : avg));
-    int rc = resolve_config(1, avg_w, 8, &opts->cfg, &c->th, &c->nw);
+    // default tiles: one call covers the tiles of all its images, so the
+    // grid is sized like one image of max_pixels pixels (seen as one row:
+    // only the pixel count selects the size class)
+    const int64_t px = opts->max_pixels;
+    const int px_w = (int)(px > 0x7fffffff ? 0x7fffffff : px);
+    int rc = resolve_config(1, px_w, 8, &opts->cfg, &c->th, &c->nw);
     if (rc != CCL_OK) {
         delete c;
         return rc;

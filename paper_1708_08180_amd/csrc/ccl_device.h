@@ -127,11 +127,18 @@ __device__ __forceinline__ void lds_st(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Global forest accessors for the concurrent boundary phase.  Loads are
-// agent-scope atomics so a wavefront on one XCD sees links made through the
-// memory-side atomics of another XCD instead of a stale line in its own L2.
+// Global forest accessors for the concurrent boundary phase.  Links are
+// made with agent-scope atomicMin, which acts on the one coherent copy.
+// Finds read through the caches (g_ld): a read may return an older parent
+// than the current one, but the forest only ever gets coarser -- a parent
+// is only replaced by one of its own ancestors, always a smaller index --
+// so an old parent is still an ancestor, every walk still ends, and a node
+// taken for a root by mistake is caught by the value the linking atomicMin
+// returns (the link is then retried from there).  Reading the hot roots of
+// large components from the caches instead of memory is what keeps the
+// phase from serializing on them.
 __device__ __forceinline__ uint32_t g_ld(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ uint32_t g_min(uint32_t *p, uint32_t v) {
     return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -105,21 +105,22 @@ def test_autotune_validation_without_device():
 
 def test_tuning_table_roundtrip(tmp_path):
     binding.tuning_clear()
-    assert binding.tuning_get(4096, 4096, 8) == (32, 2)       # built-in default
+    assert binding.tuning_get(4096, 4096, 8) == (64, 4)       # built-in default, large images
+    assert binding.tuning_get(1080, 1920, 8) == (32, 8)       # built-in default, below 2^22 px
     src = tmp_path / "in.jsonl"
-    src.write_text('{"class": 24, "conn": 8, "tile_h": 64, "waves": 4, "ms": 0.150000}\n'
+    src.write_text('{"class": 24, "conn": 8, "tile_h": 32, "waves": 2, "ms": 0.150000}\n'
                    '{"class": 20, "conn": 4, "tile_h": 16, "waves": 1, "ms": 0.020000}\n')
     binding.tuning_load(str(src))
-    assert binding.tuning_get(4096, 4096, 8) == (64, 4)       # 2^24 pixels -> class 24
-    assert binding.tuning_get(4096, 4096, 4) == (32, 2)       # other connectivity: default
+    assert binding.tuning_get(4096, 4096, 8) == (32, 2)       # 2^24 pixels -> class 24
+    assert binding.tuning_get(4096, 4096, 4) == (64, 4)       # other connectivity: default
     assert binding.tuning_get(1024, 1024, 4) == (16, 1)       # 2^20 pixels -> class 20
     out = tmp_path / "out.jsonl"
     binding.tuning_save(str(out))
     lines = sorted(out.read_text().strip().splitlines())
-    assert len(lines) == 2 and '"tile_h": 64' in "".join(lines)
+    assert len(lines) == 2 and '"tile_h": 32' in "".join(lines)
     bad = tmp_path / "bad.jsonl"
     bad.write_text('{"class": 24, "conn": 8, "tile_h": 48, "waves": 4, "ms": 1.0}\n')
     with pytest.raises(binding.CclError):
         binding.tuning_load(str(bad))
     binding.tuning_clear()
-    assert binding.tuning_get(4096, 4096, 8) == (32, 2)
+    assert binding.tuning_get(4096, 4096, 8) == (64, 4)
