@@ -55,10 +55,16 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    only if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+# MI355X: 256 CUs x 4 SIMDs at 2.4 GHz; a SIMD issues at most one wave64
+# vector instruction and one scalar instruction every 4 cycles.
+SIMD_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
+
+
+def stored_counters(kernel: str, workload: str):
+    """Per-launch HBM bytes and instruction counts from the committed
+    rocprofv3 counter summary, only if it was taken on the current kernel
+    sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
     try:
         with open(path) as f:
             data = json.load(f)
@@ -67,7 +73,7 @@ def stored_traffic(kernel: str, workload: str):
     ent = data.get("%s@%s" % (kernel, workload))
     if not ent or ent.get("source_digest") != kernel_source_digest():
         return None
-    return ent.get("bytes_per_launch")
+    return ent
 
 
 def time_calls(lib, args_for_call, steps, stream_handle, torch):
@@ -335,11 +341,21 @@ def main():
     t_k = head["phase"][k] * 1e-3
     alg = PHASE_BYTES_PER_PIXEL[k] * px
     achieved = alg / t_k / 1e9
+    ctr = stored_counters(PHASE_NAMES[k], "4096x4096-bern0.5-conn%d" % args.conn) \
+        if (head["H"], head["W"]) == (4096, 4096) and args.config is None else None
     roofline = {"bound": "hbm", "kernel": PHASE_NAMES[k], "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic(PHASE_NAMES[k], "4096x4096-bern0.5-conn%d" % args.conn),
+                "traffic": ctr["bytes_per_launch"] if ctr else None,
                 "alg_bytes_per_launch": int(alg),
                 "kernel_ms": round(head["phase"][k], 5)}
+    if ctr:
+        # what actually limits this kernel: instruction issue (counters per
+        # launch from the committed profile, over the live kernel time)
+        roofline["issue"] = {
+            "valu_instr": ctr["valu_instr"], "salu_instr": ctr["salu_instr"],
+            "peak_instr_per_s_each": SIMD_ISSUE_PER_S,
+            "valu_frac": round(ctr["valu_instr"] / t_k / SIMD_ISSUE_PER_S, 4),
+            "salu_frac": round(ctr["salu_instr"] / t_k / SIMD_ISSUE_PER_S, 4)}
     path_gbs = BYTES_PER_PIXEL_PATH * px / (head["ms"] * 1e-3) / 1e9
     out = {
         "metric": "Gpixels/s (4096^2 8-conn) & % HBM roofline",
