@@ -133,6 +133,22 @@ int ccl_label_2d_timed(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
                        int32_t connectivity, uint32_t *labels, const ccl_config *cfg,
                        void *stream, float *phase_ms);
 
+/*
+ * ccl_label_2d_equal -- equal-value labeling: every pixel, of any value and
+ * background included, joins the 4- or 8-neighbours whose image value equals
+ * its own (the literal "same property" test of Kernels 1 and 2, Sec. II-A/B,
+ * applied to every value class).
+ * Output: labels[y*W+x] = 1 + the smallest raster index y'*W+x' of the
+ * pixel's equal-valued component (never 0).  Arguments, layout, ownership,
+ * stream and workspace behaviour as in ccl_label_2d; cfg NULL or zeroed =
+ * default.  Compiled tile configurations: (16,4), (32,2), (32,8), (64,4),
+ * (64,8); any other cfg gives CCL_ERR_UNSUPPORTED.  The workspace is about
+ * 2 bytes per pixel larger than the binary one (up to 64 runs per row).
+ */
+int ccl_label_2d_equal(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
+                       int32_t connectivity, uint32_t *labels, const ccl_config *cfg,
+                       void *stream);
+
 /* ------------------------------------------------------------------ batch
  *
  * A context labels many images of different sizes in one call (the batched

@@ -67,6 +67,7 @@ SIGNATURES = {
                                        ctypes.POINTER(Config), _P]),
     "ccl_label_2d_timed": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, ctypes.POINTER(Config), _P,
                                           ctypes.POINTER(ctypes.c_float)]),
+    "ccl_label_2d_equal": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, ctypes.POINTER(Config), _P]),
     "ccl_shutdown": (None, []),
     "ccl_ctx_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(CtxOpts)]),
     "ccl_ctx_destroy": (ctypes.c_int, [_P]),
@@ -221,6 +222,26 @@ def label_plain(img, conn: int = 8, out=None, stream=None):
         rc = lib.ccl_label_2d(img.data_ptr(), H, W, _pitch(img), int(conn), out.data_ptr(),
                               _stream_handle(stream))
     _check(rc, "ccl_label_2d")
+    return out
+
+
+def label_equal(img, conn: int = 8, out=None, config=None, stream=None):
+    """Equal-value labeling of a 2D uint8 CUDA tensor (every value class,
+    background included): int32 tensor of 1 + the smallest raster index of
+    each pixel's equal-valued component."""
+    torch = _torch()
+    _check_image(img)
+    H, W = img.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.int32, device=img.device)
+    elif out.shape != (H, W) or out.dtype != torch.int32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor of shape (H, W)")
+    lib = load_library()
+    cfg = ctypes.byref(Config(int(config[0]), int(config[1]))) if config else None
+    with torch.cuda.device(img.device):
+        rc = lib.ccl_label_2d_equal(img.data_ptr(), H, W, _pitch(img), int(conn), out.data_ptr(),
+                                    cfg, _stream_handle(stream))
+    _check(rc, "ccl_label_2d_equal")
     return out
 
 

@@ -93,8 +93,8 @@ int resolve_config(int H, int W, int conn, const ccl_config *cfg, int *th, int *
 }
 
 ImgView make_view(const uint8_t *img, int32_t H, int32_t W, int64_t pitch, uint32_t *labels,
-                  void *ws, int th) {
-    const WsLayout l = ws_layout(H, W, th);
+                  void *ws, int th, bool equal = false) {
+    const WsLayout l = ws_layout(H, W, th, equal);
     ImgView v;
     v.img = img;
     v.labels = labels;
@@ -202,6 +202,35 @@ int ccl_label_2d_timed(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
     for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventElapsedTime(&phase_ms[i], ev[i], ev[i + 1]);
     for (int i = 0; i < 4; ++i)
         if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (e != hipSuccess) return fail_hip(e);
+    return CCL_OK;
+}
+
+int ccl_label_2d_equal(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
+                       int32_t connectivity, uint32_t *labels, const ccl_config *cfg,
+                       void *stream) {
+    int rc = validate_image(img, H, W, pitch, labels);
+    if (rc != CCL_OK) return rc;
+    if (connectivity != 4 && connectivity != 8) return CCL_ERR_UNSUPPORTED;
+    int th = 0, nw = 0;
+    if (cfg && (cfg->tile_h != 0 || cfg->waves != 0)) {
+        if (!config_supported_equal(cfg->tile_h, cfg->waves)) return CCL_ERR_UNSUPPORTED;
+        th = cfg->tile_h;
+        nw = cfg->waves;
+    } else {
+        default_config(H, W, connectivity, &th, &nw);
+        if (!config_supported_equal(th, nw)) {
+            // a tuning-table entry this mode is not compiled for: size rule
+            th = (int64_t)H * W < ((int64_t)1 << 22) ? 32 : 64;
+            nw = th == 32 ? 8 : 4;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    void *ws = nullptr;
+    rc = stream_workspace(s, ws_layout(H, W, th, true).total, &ws);
+    if (rc != CCL_OK) return rc;
+    const ImgView v = make_view(img, H, W, pitch, labels, ws, th, true);
+    const hipError_t e = launch_plain(v, th, nw, connectivity, s, nullptr, true);
     if (e != hipSuccess) return fail_hip(e);
     return CCL_OK;
 }

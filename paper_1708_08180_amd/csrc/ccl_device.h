@@ -41,7 +41,11 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;  // "no node"
 
 enum { kMaskTop = 0, kMaskBottom = 1, kMaskLeft = 2, kMaskRight = 3 };
 
-constexpr int kSlotsPerRow = 32;  // a 64-pixel row has at most 32 runs
+// Run records per tile row: a 64-pixel row has at most 32 foreground runs,
+// and at most 64 equal-value runs.
+template <bool EQ>
+__host__ __device__ constexpr int slots_per_row() { return EQ ? 64 : 32; }
+constexpr int kSlotsPerRow = slots_per_row<false>();
 
 __host__ __device__ constexpr int roots_per_tile(int th) { return 2 * kTileW + 2 * th; }
 __host__ __device__ constexpr int roots_top(int) { return 0; }
@@ -56,7 +60,7 @@ struct ImgView {
     uint64_t *masks;    // [tiles][4]
     uint32_t *roots;    // [tiles][roots_per_tile(TH)]
     uint64_t *rowmask;  // [tiles][2*TH]: row masks, then edge-root masks
-    uint16_t *slots;    // [tiles][TH][kSlotsPerRow]
+    uint16_t *slots;    // [tiles][TH][slots_per_row]
     int64_t pitch;
     int32_t H, W;
     int32_t tilesX, tilesY;
@@ -459,6 +463,100 @@ __device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, i
         if (lane_in(p.pr)) lds_union(par, node, up + bu);
     } else {
         if (lane_in(p.pm)) lds_union(par, node, up + bu - (lane_in(Su) ? 0u : 1u));
+    }
+}
+
+// ------------------------------------------- equal-value labeling (K1 part)
+//
+// Every in-image pixel takes part and a pixel joins the neighbours whose
+// image value equals its own (the kernels' literal test in Sec. II-A, all
+// value classes labeled).  Runs are maximal horizontal segments of one
+// value, so a row holds up to 64 of them.  `v` is a lane's pixel value, or
+// a value no byte can equal for lanes outside the image.
+
+// Sweep of one wavefront's band for equal-value labeling.  Each lane links
+// its run to the runs of the equal-valued cells above it (every such lane
+// proposes; the LDS atomicMin keeps the smallest root and the rare other
+// roots are joined by real unions).  Writes msk[r] = the row's run starts
+// and rinfo[r] (runs | 0x100: first run at column 0 | 0x200: last run ends
+// at column 63).
+template <int TH, int RPW, bool CONN8>
+__device__ __forceinline__ void sweep_band_eq(uint32_t *par, uint8_t *col, uint64_t *msk,
+                                              uint16_t *rinfo, const uint8_t *pix, int wave,
+                                              int lane, int wlim, int hlim) {
+    constexpr int SPR = slots_per_row<true>();
+    constexpr uint32_t kOut = 0x100u, kOutUp = 0x200u;
+    uint32_t ra = kNone, vu = kOutUp;
+    uint32_t pv[RPW];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) pv[k] = pix[(wave * RPW + k) * kTileW + lane];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+        const int r = wave * RPW + k;
+        const bool in = lane < wlim && r < hlim;
+        const uint32_t vv = in ? pv[k] : kOut;
+        const uint32_t vl = from_left(vv, kOut);
+        const uint64_t S = __ballot(in && (lane == 0 || vv != vl));
+        const bool isS = lane_in(S);
+        const uint32_t node = (uint32_t)(r * SPR) + bits_below(S) - (isS ? 0u : 1u);
+        uint32_t *pn = &par[node];
+        if (isS) {
+            lds_st(pn, node);
+            col[node] = (uint8_t)lane;
+        }
+        if (lane == 0) {
+            msk[r] = S;
+            rinfo[r] = (uint16_t)(__popcll(S) | ((S & 1ull) ? 0x100 : 0) | (wlim == 64 ? 0x200 : 0));
+        }
+        uint32_t md = in ? node : kNone;
+        if (k > 0) {
+            const uint32_t tM = in && vv == vu ? ra : kNone;
+            uint32_t tL = kNone, tR = kNone;
+            if (CONN8) {
+                const uint32_t vuL = from_left(vu, kOutUp), vuR = from_right(vu, kOutUp);
+                const uint32_t rL = from_left(ra, kNone), rR = from_right(ra, kNone);
+                tL = in && vv == vuL ? rL : kNone;
+                tR = in && vv == vuR ? rR : kNone;
+            }
+            const uint32_t tm = tM < tL ? (tM < tR ? tM : tR) : (tL < tR ? tL : tR);
+            if (tm != kNone) atomicMin(pn, tm);
+            if (in) md = lds_ld(pn);
+            const bool nM = tM != kNone && tM != md;
+            const bool nL = tL != kNone && tL != md;
+            const bool nR = tR != kNone && tR != md;
+            if (__ballot(nM || nL || nR)) {
+                if (nM) lds_union(par, tM, md);
+                if (nL) lds_union(par, tL, md);
+                if (nR) lds_union(par, tR, md);
+                if (in) md = lds_root(par, md);
+                if (isS) lds_st(pn, md);
+            }
+        }
+        ra = md;
+        vu = in ? vv : kOutUp;
+    }
+}
+
+// Band seam for equal-value labeling: the first row r of a band against the
+// last row of the band above (run starts already in msk), general unions.
+template <bool CONN8>
+__device__ __forceinline__ void merge_seam_eq(uint32_t *par, const uint64_t *msk, const uint8_t *pix,
+                                              int r, int lane, int wlim, int hlim) {
+    constexpr int SPR = slots_per_row<true>();
+    constexpr uint32_t kOut = 0x100u, kOutUp = 0x200u;
+    if (r >= hlim) return;  // wave-uniform: the whole band lies below the image
+    const bool in = lane < wlim;
+    const uint32_t vv = in ? pix[r * kTileW + lane] : kOut;
+    const uint32_t vu = in ? pix[(r - 1) * kTileW + lane] : kOutUp;
+    const uint64_t S = uniform64(msk[r]), Su = uniform64(msk[r - 1]);
+    const uint32_t node = (uint32_t)(r * SPR) + bits_below(S) - (lane_in(S) ? 0u : 1u);
+    const uint32_t up = (uint32_t)((r - 1) * SPR) + bits_below(Su) - (lane_in(Su) ? 0u : 1u);
+    if (in && vv == vu) lds_union(par, node, up);
+    if (CONN8) {
+        const uint32_t vuL = from_left(vu, kOutUp), vuR = from_right(vu, kOutUp);
+        const uint32_t upL = from_left(up, kNone), upR = from_right(up, kNone);
+        if (in && vv == vuL) lds_union(par, node, upL);
+        if (in && vv == vuR) lds_union(par, node, upR);
     }
 }
 

@@ -24,10 +24,14 @@ struct BatchKernels {
 };
 bool batch_kernels(int th, int nw, int conn, BatchKernels *out);
 
+// True when (tile_h, waves) is compiled for equal-value labeling.
+bool config_supported_equal(int th, int nw);
+
 // Enqueue the three phases for one image on `s`.  With ev != nullptr,
 // ev[0..3] are recorded before phase 1, between the phases and after phase 3.
+// equal: label every equal-value class instead of the nonzero foreground.
 hipError_t launch_plain(const ImgView &v, int th, int nw, int conn, hipStream_t s,
-                        hipEvent_t *ev = nullptr);
+                        hipEvent_t *ev = nullptr, bool equal = false);
 
 // Workspace layout for one image: edge masks, edge-cell roots, row masks
 // (row foreground and edge-root masks), run slots.
@@ -42,7 +46,7 @@ struct WsLayout {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-inline WsLayout ws_layout(int H, int W, int th) {
+inline WsLayout ws_layout(int H, int W, int th, bool equal = false) {
     WsLayout l;
     const size_t tx = ((size_t)W + kTileW - 1) / kTileW;
     const size_t ty = ((size_t)H + th - 1) / th;
@@ -50,7 +54,8 @@ inline WsLayout ws_layout(int H, int W, int th) {
     l.mask_bytes = align_up(l.tiles * 4 * sizeof(uint64_t), 256);
     l.root_bytes = align_up(l.tiles * (size_t)roots_per_tile(th) * sizeof(uint32_t), 256);
     l.rowmask_bytes = align_up(l.tiles * 2 * (size_t)th * sizeof(uint64_t), 256);
-    l.slot_bytes = align_up(l.tiles * (size_t)th * kSlotsPerRow * sizeof(uint16_t), 256);
+    const size_t spr = equal ? (size_t)slots_per_row<true>() : (size_t)slots_per_row<false>();
+    l.slot_bytes = align_up(l.tiles * (size_t)th * spr * sizeof(uint16_t), 256);
     l.total = l.mask_bytes + l.root_bytes + l.rowmask_bytes + l.slot_bytes;
     return l;
 }

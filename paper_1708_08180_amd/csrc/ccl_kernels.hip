@@ -37,56 +37,72 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nb) {
 
 // ------------------------------------------------------------- local merge
 
-template <int TH>
+template <int TH, bool EQ>
 struct K1Lds {
-    uint32_t par[TH * kSlotsPerRow];  // run-indexed parents
-    uint8_t col[TH * kSlotsPerRow];   // first column of every run
-    uint64_t msk[TH];                 // row masks
-    uint64_t flg[TH];                 // per row: local roots of edge-touching components
-    uint8_t rinfo[TH];                // runs per row | first run at column 0 | last at 63
+    static constexpr int SPR = slots_per_row<EQ>();
+    uint32_t par[TH * SPR];  // run-indexed parents
+    uint8_t col[TH * SPR];   // first column of every run
+    uint64_t msk[TH];        // per row: foreground mask (binary) / run starts (equal-value)
+    uint64_t flg[TH];        // per row: local roots of edge-touching components
+    uint16_t rinfo[TH];      // runs | 0x100: first run at column 0 | 0x200: last ends at 63
+    alignas(16) uint8_t pix[EQ ? TH * kTileW : 16];  // the tile's bytes (equal-value only)
 };
 
-// Kernel 1 body for tile t of image v.  Ends after a workgroup barrier, so
-// the caller may reuse the LDS for the next tile.
-template <int TH, int NW, bool CONN8>
-__device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH> &sh) {
+// Kernel 1 body for tile t of image v.  EQ selects equal-value labeling
+// (every value class) instead of binary foreground labeling.  Ends after a
+// workgroup barrier, so the caller may reuse the LDS for the next tile.
+template <int TH, int NW, bool CONN8, bool EQ>
+__device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, EQ> &sh) {
+    constexpr int SPR = slots_per_row<EQ>();
     constexpr int RPW = TH / NW;
     constexpr int NT = NW * 64;
     constexpr int CH = TH * 4;                  // 16-byte chunks per tile
     constexpr int LPT = (CH + NT - 1) / NT;     // chunks per thread
-    constexpr int NODES = TH * kSlotsPerRow;    // run-indexed nodes per tile
+    constexpr int NODES = TH * SPR;             // run-indexed nodes per tile
     constexpr int NPT = (NODES + NT - 1) / NT;  // nodes per thread
     uint32_t *par = sh.par;
     uint8_t *col = sh.col;
     uint64_t *msk = sh.msk;
     uint64_t *flg = sh.flg;
-    uint8_t *rinfo = sh.rinfo;
+    uint16_t *rinfo = sh.rinfo;
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t TX = (uint32_t)v.tilesX;
     const int tx = (int)(t % TX), ty = (int)(t / TX);
     const bool hasUp = ty > 0, hasDown = ty + 1 < v.tilesY;
     const bool hasLeft = tx > 0, hasRight = tx + 1 < v.tilesX;
+    // columns / rows of the tile inside the image
+    const int wlim = min(kTileW, v.W - tx * kTileW), hlim = min(TH, v.H - ty * TH);
 
-    // row masks into LDS (16 pixels per chunk)
+    // the tile's rows: row masks (binary) or the raw bytes (equal-value)
 #pragma unroll
     for (int i = 0; i < LPT; ++i) {
         const int c = tid + i * NT;
-        if (c < CH)
-            ((uint16_t *)msk)[c] = (uint16_t)nonzero_bytes16(load_chunk(v, tx, ty, TH, c >> 2, c & 3));
+        if (c < CH) {
+            const uint4 b = load_chunk(v, tx, ty, TH, c >> 2, c & 3);
+            if (EQ) ((uint4 *)sh.pix)[c] = b;
+            else ((uint16_t *)msk)[c] = (uint16_t)nonzero_bytes16(b);
+        }
     }
     if (tid < TH) flg[tid] = 0ull;
     __syncthreads();
-    // per-row run counts and edge bits, one row per thread (read after the
-    // barriers that follow the sweep)
-    if (tid < TH) {
-        const uint64_t d = msk[tid];
-        rinfo[tid] = (uint8_t)(__popcll(run_starts(d)) | ((d & 1ull) ? 0x40 : 0) |
-                               ((d >> 63) ? 0x80 : 0));
+    if (EQ) {
+        sweep_band_eq<TH, RPW, CONN8>(par, col, msk, rinfo, sh.pix, wave, lane, wlim, hlim);
+    } else {
+        // per-row run counts and edge bits, one row per thread (read after
+        // the barriers that follow the sweep)
+        if (tid < TH) {
+            const uint64_t d = msk[tid];
+            rinfo[tid] = (uint16_t)(__popcll(run_starts(d)) | ((d & 1ull) ? 0x100 : 0) |
+                                    ((d >> 63) ? 0x200 : 0));
+        }
+        sweep_band<TH, RPW, CONN8>(par, col, msk, wave, lane);
     }
-    sweep_band<TH, RPW, CONN8>(par, col, msk, wave, lane);
     if (NW > 1) {
         __syncthreads();
-        if (wave > 0) merge_seam<CONN8>(par, msk, wave * RPW);
+        if (wave > 0) {
+            if (EQ) merge_seam_eq<CONN8>(par, msk, sh.pix, wave * RPW, lane, wlim, hlim);
+            else merge_seam<CONN8>(par, msk, wave * RPW);
+        }
     }
     __syncthreads();
 
@@ -94,23 +110,23 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH> 
     // its owner alone stores it, so par[n] is the root afterwards; the run's
     // record (the root's tile-local pixel) goes out, and edge runs mark
     // their root pixel in the edge-root masks.
-    uint16_t *sl = v.slots + (size_t)t * TH * kSlotsPerRow;
+    uint16_t *sl = v.slots + (size_t)t * TH * SPR;
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
         const int n = tid + i * NT;
         if (n >= NODES) break;
-        const int r = n >> 5, k = n & 31;
+        const int r = n / SPR, k = n % SPR;
         const uint32_t info = rinfo[r];
-        const int runs = (int)(info & 63u);
+        const int runs = (int)(info & 0x7Fu);
         if (k >= runs) continue;
         const uint32_t root = lds_root(par, (uint32_t)n);
         if (root != (uint32_t)n) lds_st(&par[n], root);
         const uint32_t rc = col[root];
-        sl[n] = (uint16_t)((root >> 5) * kTileW + rc);
+        sl[n] = (uint16_t)((root / SPR) * kTileW + rc);
         const bool edge = (r == 0 && hasUp) || (r == TH - 1 && hasDown) ||
-                          (k == 0 && (info & 0x40u) && hasLeft) ||
-                          (k == runs - 1 && (info & 0x80u) && hasRight);
-        if (edge) atomicOr((unsigned long long *)&flg[root >> 5], 1ull << rc);
+                          (k == 0 && (info & 0x100u) && hasLeft) ||
+                          (k == runs - 1 && (info & 0x200u) && hasRight);
+        if (edge) atomicOr((unsigned long long *)&flg[root / SPR], 1ull << rc);
     }
     __syncthreads();
     if (tid < TH) {
@@ -123,35 +139,40 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH> 
     if (wave == 0) {
         uint64_t *mk = v.masks + (size_t)t * 4;
         uint32_t *rt = v.roots + (size_t)t * roots_per_tile(TH);
-        const uint64_t mTop = uniform64(msk[0]);
-        const uint64_t mBot = uniform64(msk[TH - 1]);
+        // cells taking part in the top / bottom row, run starts of those rows
+        const uint64_t cols = wlim == 64 ? ~0ull : ((1ull << wlim) - 1ull);
+        const uint64_t mTop = EQ ? cols : uniform64(msk[0]);
+        const uint64_t mBot = EQ ? (TH - 1 < hlim ? cols : 0ull) : uniform64(msk[TH - 1]);
+        const uint64_t sTop = EQ ? uniform64(msk[0]) : run_starts(mTop);
+        const uint64_t sBot = EQ ? uniform64(msk[TH - 1]) : run_starts(mBot);
         // global index of the root pixel of run node n
         auto root_g = [&](uint32_t n) {
             const uint32_t root = lds_ld(&par[n]);
-            return global_index(v, tx, ty, TH, (root >> 5) * kTileW + col[root]);
+            return global_index(v, tx, ty, TH, (root / SPR) * kTileW + col[root]);
         };
         auto put = [&](uint32_t *dst, uint32_t g) {
             *dst = g;
             v.labels[g] = g + 1u;
         };
         if (hasUp && lane_in(mTop)) {
-            const uint64_t S = run_starts(mTop);
-            const uint32_t n = bits_below(S) - (lane_in(S) ? 0u : 1u);
+            const uint32_t n = bits_below(sTop) - (lane_in(sTop) ? 0u : 1u);
             put(&rt[roots_top(TH) + lane], root_g(n));
         }
         if (hasDown && lane_in(mBot)) {
-            const uint64_t S = run_starts(mBot);
-            const uint32_t n = (uint32_t)((TH - 1) * kSlotsPerRow) + bits_below(S) -
-                               (lane_in(S) ? 0u : 1u);
+            const uint32_t n = (uint32_t)((TH - 1) * SPR) + bits_below(sBot) -
+                               (lane_in(sBot) ? 0u : 1u);
             put(&rt[roots_bottom(TH) + lane], root_g(n));
         }
+        // per row (lane = row): cells in the left / right column, last run
         const uint64_t mr = lane < TH ? msk[lane] : 0ull;
-        const bool lb = (mr & 1ull) != 0, rb = (mr >> 63) != 0;
+        const bool rowIn = lane < hlim;
+        const bool lb = EQ ? rowIn : (mr & 1ull) != 0;
+        const bool rb = EQ ? (rowIn && wlim == 64) : (mr >> 63) != 0;
+        const int lastRun = __popcll(EQ ? mr : run_starts(mr)) - 1;
         const uint64_t mLeft = __ballot(lb), mRight = __ballot(rb);
-        if (hasLeft && lb) put(&rt[roots_left(TH) + lane], root_g((uint32_t)(lane * kSlotsPerRow)));
+        if (hasLeft && lb) put(&rt[roots_left(TH) + lane], root_g((uint32_t)(lane * SPR)));
         if (hasRight && rb)
-            put(&rt[roots_right(TH) + lane],
-                root_g((uint32_t)(lane * kSlotsPerRow + __popcll(run_starts(mr)) - 1)));
+            put(&rt[roots_right(TH) + lane], root_g((uint32_t)(lane * SPR + lastRun)));
         if (lane == 0) {
             mk[kMaskTop] = mTop;
             mk[kMaskBottom] = mBot;
@@ -227,6 +248,67 @@ __device__ __forceinline__ void k2_tile(const ImgView &v, uint32_t t) {
     union_requests<4>(v.labels, v.n, A, B);
 }
 
+// Equal-value boundary analysis for tile t: like k2_tile, but a pair of
+// cells across the edge is merged when their image values are equal (read
+// straight from the image), and every such pair is proposed -- the
+// deduplication keeps one union per distinct pair of roots.
+template <int TH, bool CONN8>
+__device__ __forceinline__ void k2_tile_eq(const ImgView &v, uint32_t t) {
+    constexpr int RT = roots_per_tile(TH);
+    constexpr uint32_t kOut = 0x100u, kOutUp = 0x200u;  // no byte equals these
+    const int lane = lane_id();
+    const uint32_t TX = (uint32_t)v.tilesX;
+    const uint32_t tx = t % TX, ty = t / TX;
+    const bool hasT = ty > 0, hasL = tx > 0, hasR = tx + 1u < TX;
+    const int x0 = (int)tx * kTileW, y0 = (int)ty * TH;
+    const int wlim = min(kTileW, v.W - x0), hlim = min(TH, v.H - y0);
+    const uint32_t *rts = v.roots;
+    uint32_t vT = kOut, vU = kOutUp, vUL = kOutUp, vUR = kOutUp, vC = kOut, vN = kOutUp;
+    uint32_t aT = kNone, rT = kNone, eTL = kNone, eTR = kNone, aL = kNone, rL = kNone;
+    if (hasT) {
+        const uint32_t tu = t - TX;
+        const uint8_t *row = v.img + (int64_t)y0 * v.pitch + x0;  // this tile's top row
+        const uint8_t *up = row - v.pitch;                         // the row above it
+        if (lane < wlim) {
+            vT = row[lane];
+            vU = up[lane];
+            aT = rts[(size_t)t * RT + roots_top(TH) + lane];
+            rT = rts[(size_t)tu * RT + roots_bottom(TH) + lane];
+        }
+        if (hasL) {
+            vUL = up[-1];
+            eTL = rts[(size_t)(tu - 1u) * RT + roots_bottom(TH) + 63];
+        }
+        if (hasR) {
+            vUR = up[kTileW];
+            eTR = rts[(size_t)(tu + 1u) * RT + roots_bottom(TH)];
+        }
+    }
+    if (hasL && lane < hlim) {
+        const uint8_t *p = v.img + (int64_t)(y0 + lane) * v.pitch + x0;
+        vC = p[0];
+        vN = p[-1];
+        aL = rts[(size_t)t * RT + roots_left(TH) + lane];
+        rL = rts[(size_t)(t - 1u) * RT + roots_right(TH) + lane];
+    }
+    // neighbours across the edge: above-left / above-right (top edge), the
+    // left cells of the rows above / below (left edge, inside the tile rows)
+    const uint32_t vUl = from_left(vU, vUL), vUr = from_right(vU, vUR);
+    const uint32_t bTl = from_left(rT, eTL), bTr = from_right(rT, eTR);
+    const uint32_t vNu = from_left(vN, kOutUp), vNd = from_right(vN, kOutUp);
+    const uint32_t bLu = from_left(rL, kNone), bLd = from_right(rL, kNone);
+    uint32_t A[6], B[6];
+    A[0] = A[1] = A[2] = aT;
+    A[3] = A[4] = A[5] = aL;
+    B[0] = vT == vU ? rT : kNone;
+    B[1] = CONN8 && vT == vUl ? bTl : kNone;
+    B[2] = CONN8 && vT == vUr ? bTr : kNone;
+    B[3] = vC == vN ? rL : kNone;
+    B[4] = CONN8 && vC == vNu ? bLu : kNone;
+    B[5] = CONN8 && vC == vNd ? bLd : kNone;
+    union_requests<6>(v.labels, v.n, A, B);
+}
+
 // ----------------------------------------------------------------- link
 
 // Link body for tile t (Sec. II-C): the local merge left the tile's row
@@ -238,8 +320,9 @@ __device__ __forceinline__ void k2_tile(const ImgView &v, uint32_t t) {
 // unflagged roots are already final.  Then every pixel reads its root's
 // entry; output rows are full 256-byte lines.  Ends after a workgroup
 // barrier.
-template <int TH, int NW>
+template <int TH, int NW, bool EQ>
 __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *fin) {
+    constexpr int SPR = slots_per_row<EQ>();
     constexpr int RPW = TH / NW;
     const uint32_t TX = (uint32_t)v.tilesX;
     const uint32_t tx = t % TX, ty = t / TX;
@@ -247,9 +330,13 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t W = (uint32_t)v.W;
     const uint64_t *rm = v.rowmask + (size_t)t * 2 * TH + wave * RPW;
-    const uint16_t *sl = v.slots + (size_t)t * TH * kSlotsPerRow + wave * RPW * kSlotsPerRow;
+    const uint16_t *sl = v.slots + (size_t)t * TH * SPR + wave * RPW * SPR;
     // global index of the tile's pixel (0, 0); every label fits in 32 bits
     const uint32_t origin = ty * (uint32_t)TH * W + tx * (uint32_t)kTileW;
+    // equal-value: every in-image pixel takes part (rows hold run starts)
+    const int wlim = min(kTileW, v.W - (int)tx * kTileW);
+    const uint64_t cols = wlim == 64 ? ~0ull : ((1ull << wlim) - 1ull);
+    const int rows_in = v.H - (int)ty * TH - wave * RPW;
     uint64_t m[RPW], f[RPW];
     uint32_t rec[RPW];
 #pragma unroll
@@ -261,11 +348,12 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *
     for (int k = 0; k < RPW; ++k) {
         // run of this lane (rank among the row's run starts at or below it;
         // background lanes read some slot of the row and discard it)
-        const uint64_t S = run_starts(m[k]);
+        const uint64_t d = EQ ? (k < rows_in ? cols : 0ull) : m[k];
+        const uint64_t S = EQ ? m[k] : run_starts(m[k]);
         const uint32_t below = bits_below(S) + (lane_in(S) ? 1u : 0u);
         const uint32_t rank = below ? below - 1u : 0u;
-        const uint32_t r = sl[k * kSlotsPerRow + rank];
-        rec[k] = lane_in(m[k]) ? r : kNone;
+        const uint32_t r = sl[k * SPR + rank];
+        rec[k] = lane_in(d) ? r : kNone;
     }
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
@@ -290,23 +378,24 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *
 
 // ------------------------------------------------------ single-image kernels
 
-template <int TH, int NW, bool CONN8>
+template <int TH, int NW, bool CONN8, bool EQ>
 __global__ void __launch_bounds__(NW * 64) k1_local_merge(ImgView v) {
-    __shared__ K1Lds<TH> sh;
-    k1_tile<TH, NW, CONN8>(v, xcd_remap(blockIdx.x, gridDim.x), sh);
+    __shared__ K1Lds<TH, EQ> sh;
+    k1_tile<TH, NW, CONN8, EQ>(v, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 
-template <int TH, bool CONN8>
+template <int TH, bool CONN8, bool EQ>
 __global__ void __launch_bounds__(256) k2_boundary(ImgView v, uint32_t tiles) {
     const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4u + (threadIdx.x >> 6)));
     if (t >= tiles) return;  // wave-uniform
-    k2_tile<TH, CONN8>(v, t);
+    if (EQ) k2_tile_eq<TH, CONN8>(v, t);
+    else k2_tile<TH, CONN8>(v, t);
 }
 
-template <int TH, int NW>
+template <int TH, int NW, bool EQ>
 __global__ void __launch_bounds__(NW * 64) k3_link(ImgView v) {
     __shared__ uint32_t fin[TH * kTileW];
-    k3_tile<TH, NW>(v, xcd_remap(blockIdx.x, gridDim.x), fin);
+    k3_tile<TH, NW, EQ>(v, xcd_remap(blockIdx.x, gridDim.x), fin);
 }
 
 // ------------------------------------------------------------ batch kernels
@@ -352,13 +441,13 @@ __device__ __forceinline__ ImgView batch_view(const BatchImage &b, const BatchWs
 // sizes the grids for every call.
 template <int TH, int NW, bool CONN8>
 __global__ void __launch_bounds__(NW * 64) k1_batch(BatchArgs a) {
-    __shared__ K1Lds<TH> sh;
+    __shared__ K1Lds<TH, false> sh;
     const uint32_t g = xcd_remap(blockIdx.x, gridDim.x);
     if (g >= a.tiles) return;  // workgroup-uniform
     const uint32_t i = batch_image_of(a, g);
     if (threadIdx.x == 0) a.w.tile_img[g] = i;
     const BatchImage &d = a.descs[i];
-    k1_tile<TH, NW, CONN8>(batch_view<TH>(d, a.w), g - d.tile_base, sh);
+    k1_tile<TH, NW, CONN8, false>(batch_view<TH>(d, a.w), g - d.tile_base, sh);
 }
 
 template <int TH, bool CONN8>
@@ -375,7 +464,7 @@ __global__ void __launch_bounds__(NW * 64) k3_batch(BatchArgs a) {
     const uint32_t g = xcd_remap(blockIdx.x, gridDim.x);
     if (g >= a.tiles) return;  // workgroup-uniform
     const BatchImage &d = a.descs[a.w.tile_img[g]];
-    k3_tile<TH, NW>(batch_view<TH>(d, a.w), g - d.tile_base, fin);
+    k3_tile<TH, NW, false>(batch_view<TH>(d, a.w), g - d.tile_base, fin);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -387,18 +476,18 @@ constexpr int link_waves() {
     return TH / 16;
 }
 
-template <int TH, int NW, bool CONN8>
+template <int TH, int NW, bool CONN8, bool EQ>
 static hipError_t launch_plain_t(const ImgView &v, hipStream_t stream, hipEvent_t *ev) {
     const uint32_t tiles = (uint32_t)v.tilesX * (uint32_t)v.tilesY;
     if (ev) (void)hipEventRecord(ev[0], stream);
-    hipLaunchKernelGGL((k1_local_merge<TH, NW, CONN8>), dim3(tiles), dim3(NW * 64), 0, stream, v);
+    hipLaunchKernelGGL((k1_local_merge<TH, NW, CONN8, EQ>), dim3(tiles), dim3(NW * 64), 0, stream, v);
     if (ev) (void)hipEventRecord(ev[1], stream);
     if (tiles > 1)
-        hipLaunchKernelGGL((k2_boundary<TH, CONN8>), dim3((tiles + 3) / 4), dim3(256), 0, stream,
+        hipLaunchKernelGGL((k2_boundary<TH, CONN8, EQ>), dim3((tiles + 3) / 4), dim3(256), 0, stream,
                            v, tiles);
     if (ev) (void)hipEventRecord(ev[2], stream);
     constexpr int NW3 = link_waves<TH>();
-    hipLaunchKernelGGL((k3_link<TH, NW3>), dim3(tiles), dim3(NW3 * 64), 0, stream, v);
+    hipLaunchKernelGGL((k3_link<TH, NW3, EQ>), dim3(tiles), dim3(NW3 * 64), 0, stream, v);
     if (ev) (void)hipEventRecord(ev[3], stream);
     return hipGetLastError();
 }
@@ -427,10 +516,32 @@ bool config_supported(int th, int nw) {
     X(16, 1) X(16, 2) X(16, 4) X(16, 8) X(16, 16) X(32, 1) X(32, 2) X(32, 4) X(32, 8) X(32, 16) \
         X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(64, 16)
 
-hipError_t launch_plain(const ImgView &v, int th, int nw, int conn, hipStream_t s, hipEvent_t *ev) {
-#define CCL_CASE(T, N)                                                                   \
-    if (th == T && nw == N)                                                              \
-        return conn == 8 ? launch_plain_t<T, N, true>(v, s, ev) : launch_plain_t<T, N, false>(v, s, ev);
+// Tile configurations compiled for equal-value labeling.
+#define CCL_FOR_EACH_EQ_CONFIG(X) X(16, 4) X(32, 2) X(32, 8) X(64, 4) X(64, 8)
+
+bool config_supported_equal(int th, int nw) {
+#define CCL_CASE(T, N) \
+    if (th == T && nw == N) return true;
+    CCL_FOR_EACH_EQ_CONFIG(CCL_CASE)
+#undef CCL_CASE
+    return false;
+}
+
+hipError_t launch_plain(const ImgView &v, int th, int nw, int conn, hipStream_t s, hipEvent_t *ev,
+                        bool equal) {
+    if (equal) {
+#define CCL_CASE(T, N)                                                        \
+    if (th == T && nw == N)                                                   \
+        return conn == 8 ? launch_plain_t<T, N, true, true>(v, s, ev)         \
+                         : launch_plain_t<T, N, false, true>(v, s, ev);
+        CCL_FOR_EACH_EQ_CONFIG(CCL_CASE)
+#undef CCL_CASE
+        return hipErrorInvalidValue;
+    }
+#define CCL_CASE(T, N)                                                        \
+    if (th == T && nw == N)                                                   \
+        return conn == 8 ? launch_plain_t<T, N, true, false>(v, s, ev)        \
+                         : launch_plain_t<T, N, false, false>(v, s, ev);
     CCL_FOR_EACH_CONFIG(CCL_CASE)
 #undef CCL_CASE
     return hipErrorInvalidValue;

@@ -57,6 +57,26 @@ def test_invalid_arguments(args, code):
     assert lib.ccl_label_2d(*args) == code
 
 
+@pytest.mark.parametrize("args,code", [
+    ((None, 4, 4, 4, 8, FAKE, None, None), 1),        # null image
+    ((FAKE, 4, 4, 4, 8, None, None, None), 1),        # null labels
+    ((FAKE, 4, 8, 7, 8, FAKE, None, None), 1),        # pitch < W
+    ((FAKE, 4, 4, 4, 6, FAKE, None, None), 2),        # connectivity 6
+    ((FAKE, 65536, 65537, 65537, 8, FAKE, None, None), 3),  # H*W > 2^32-1
+])
+def test_equal_invalid_arguments(args, code):
+    lib = binding.load_library()
+    assert lib.ccl_label_2d_equal(*args) == code
+
+
+def test_equal_config_validation():
+    # only (16,4) (32,2) (32,8) (64,4) (64,8) are compiled for equal-value labeling
+    lib = binding.load_library()
+    for th, nw in ((64, 1), (64, 16), (16, 1), (48, 4)):
+        cfg = binding.Config(th, nw)
+        assert lib.ccl_label_2d_equal(FAKE, 64, 64, 64, 8, FAKE, ctypes.byref(cfg), None) == 2
+
+
 def test_ex_validation():
     lib = binding.load_library()
     cfg = binding.Config(48, 4)
