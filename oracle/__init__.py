@@ -53,6 +53,10 @@ def _get():
             fn.restype = ctypes.c_int
             fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                            ctypes.c_int, ctypes.c_void_p]
+        lib.oracle_stats_2d.restype = ctypes.c_int
+        lib.oracle_stats_2d.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
         _lib = lib
     return _lib
 
@@ -88,3 +92,31 @@ def label(img: np.ndarray, conn: int = 8) -> np.ndarray:
 def label_equal(img: np.ndarray, conn: int = 8) -> np.ndarray:
     """Labels of every equal-value class (background included): 1 + min raster index."""
     return _run2d("oracle_label_2d_equal", img, conn)
+
+
+# One record per component (layout of the C struct oracle_component).
+STATS_DTYPE = np.dtype([("label", "<u4"), ("area", "<u4"), ("x_min", "<u4"), ("y_min", "<u4"),
+                        ("x_max", "<u4"), ("y_max", "<u4"), ("sum_x", "<u8"), ("sum_y", "<u8")])
+
+
+def stats(img: np.ndarray, conn: int = 8, equal: bool = False) -> np.ndarray:
+    """Per-component statistics in increasing label order: label, area,
+    inclusive bounding box, and the sums of column and row indices
+    (centroid = sum / area).  equal=True uses equal-value components."""
+    img = np.asarray(img)
+    if img.ndim != 2 or img.dtype != np.uint8:
+        raise ValueError("expected a 2D uint8 image")
+    img = np.ascontiguousarray(img)
+    H, W = img.shape
+    lib = _get()
+    n = ctypes.c_int64(0)
+    rc = lib.oracle_stats_2d(img.ctypes.data, H, W, W, int(conn), 1 if equal else 0, None, 0,
+                             ctypes.byref(n))
+    if rc != 0:
+        raise ValueError("oracle_stats_2d failed with code %d" % rc)
+    out = np.zeros(n.value, dtype=STATS_DTYPE)
+    rc = lib.oracle_stats_2d(img.ctypes.data, H, W, W, int(conn), 1 if equal else 0,
+                             out.ctypes.data if n.value else None, n.value, ctypes.byref(n))
+    if rc != 0:
+        raise ValueError("oracle_stats_2d failed with code %d" % rc)
+    return out

@@ -111,3 +111,72 @@ int oracle_label_2d_equal(const uint8_t *img, int64_t H, int64_t W,
 {
     return flood_2d(img, H, W, pitch, conn, 1, out);
 }
+
+/* Per-component statistics of the labeling (the applications' quantities:
+ * size and location of each component).  One record per component, in
+ * increasing label order:
+ *   label = 1 + smallest raster index of the component
+ *   area  = number of pixels
+ *   x_min, y_min, x_max, y_max = bounding box (inclusive)
+ *   sum_x, sum_y = sums of the pixels' column and row indices (centroid =
+ *                  sum / area)
+ * mode 0 = binary foreground components, mode 1 = equal-value components.
+ * Labels are computed by the flood fill above; a second raster pass then
+ * visits the components' pixels.  Because a label is the raster index of its
+ * component's first pixel, the components appear in increasing label order
+ * the first time each is met, which gives every component its record index.
+ * Records beyond `capacity` are counted in *n but not written. */
+typedef struct oracle_component {
+    uint32_t label, area, x_min, y_min, x_max, y_max;
+    uint64_t sum_x, sum_y;
+} oracle_component;
+
+int oracle_stats_2d(const uint8_t *img, int64_t H, int64_t W, int64_t pitch, int conn,
+                    int mode, oracle_component *out, int64_t capacity, int64_t *n)
+{
+    if (!n || capacity < 0 || (capacity > 0 && !out) || (mode != 0 && mode != 1))
+        return ORACLE_EINVAL;
+    if (H <= 0 || W <= 0 || H * W > (int64_t)0xFFFFFFFFll)
+        return ORACLE_EINVAL;
+    const int64_t npx = H * W;
+    uint32_t *lab = (uint32_t *)malloc((size_t)npx * sizeof(uint32_t));
+    uint32_t *rec = (uint32_t *)malloc((size_t)npx * sizeof(uint32_t));
+    if (!lab || !rec) {
+        free(lab);
+        free(rec);
+        return ORACLE_ENOMEM;
+    }
+    int rc = flood_2d(img, H, W, pitch, conn, mode, lab);
+    int64_t count = 0;
+    for (int64_t p = 0; rc == ORACLE_OK && p < npx; ++p) {
+        const uint32_t L = lab[p];
+        if (L == 0)
+            continue;
+        const uint32_t root = L - 1;
+        if (root == (uint32_t)p)
+            rec[p] = (uint32_t)count++;  /* first pixel of a new component */
+        const uint32_t c = rec[root];
+        if ((int64_t)c >= capacity)
+            continue;
+        const uint32_t x = (uint32_t)(p % W), y = (uint32_t)(p / W);
+        oracle_component *s = &out[c];
+        if (root == (uint32_t)p) {
+            s->label = L;
+            s->area = 0;
+            s->x_min = s->x_max = x;
+            s->y_min = s->y_max = y;
+            s->sum_x = s->sum_y = 0;
+        }
+        s->area += 1;
+        if (x < s->x_min) s->x_min = x;
+        if (x > s->x_max) s->x_max = x;
+        if (y < s->y_min) s->y_min = y;
+        if (y > s->y_max) s->y_max = y;
+        s->sum_x += x;
+        s->sum_y += y;
+    }
+    free(lab);
+    free(rec);
+    *n = count;
+    return rc;
+}
