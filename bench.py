@@ -233,6 +233,43 @@ def bench_serve(args, torch, log):
             "plain": plain_pts, "batched": batch_pts}
 
 
+def bench_extensions(img, conn, torch, binding, reps=50):
+    """Equal-value labeling of the same image and per-component statistics
+    of its labels, event-timed on the work stream (parity is in the tests)."""
+    stream = torch.cuda.current_stream()
+    d = torch.from_numpy(img).cuda()
+    H, W = img.shape
+    lab = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms_eq = timed(lambda: binding.label_equal(d, conn, out=lab))
+    binding.label(d, conn, out=lab)
+    n = len(binding.component_stats(lab))
+    lib = binding.load_library()
+    recs = torch.empty(max(1, n) * binding.COMPONENT_BYTES, dtype=torch.uint8, device="cuda")
+    n_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    ms_st = timed(lambda: lib.ccl_component_stats(lab.data_ptr(), H, W, recs.data_ptr(), n,
+                                                  n_dev.data_ptr(), sh))
+    px = H * W
+    return {"equal_value_labeling": {"ms": round(ms_eq, 5), "gpix_s": round(px / ms_eq / 1e6, 2),
+                                     "note": "every value class of the same image, background included"},
+            "component_stats": {"ms": round(ms_st, 5), "components": n,
+                                "gpix_s": round(px / ms_st / 1e6, 2),
+                                "note": "area, bounding box, coordinate sums of every component of its labels"}}
+
+
 def make_workload(name):
     from paper_1708_08180_amd import workloads as wl
 
@@ -389,6 +426,8 @@ def main():
                                "gpix_median": round(statistics.median(rates), 3),
                                "gpix_max": round(max(rates), 3),
                                "cells": {r["name"]: round(v, 3) for r, v in zip(results, rates)}}
+    if args.workload == "headline":
+        out["extensions"] = bench_extensions(head["img"], args.conn, torch, binding)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on the host (about %.0f s)" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(head["img"], args.conn, head["labels"], args.cpu_seconds)

@@ -149,6 +149,41 @@ int ccl_label_2d_equal(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
                        int32_t connectivity, uint32_t *labels, const ccl_config *cfg,
                        void *stream);
 
+/* ------------------------------------------------------------ statistics
+ *
+ * Per-component statistics of a canonical labeling (the output of
+ * ccl_label_2d or ccl_label_2d_equal): the size and location of every
+ * component, the quantities the paper's introduction lists as the uses of
+ * the labels. */
+
+/* One component: label = 1 + smallest raster index of the component; area
+ * = pixel count; inclusive bounding box; sums of the pixels' column (x) and
+ * row (y) indices, so the centroid is (sum_x / area, sum_y / area). */
+typedef struct ccl_component {
+    uint32_t label, area;
+    uint32_t x_min, y_min, x_max, y_max;
+    uint64_t sum_x, sum_y;
+} ccl_component;
+
+/*
+ * ccl_component_stats -- statistics of every component of `labels`.
+ * labels    DEVICE, H x W u32, row stride W: a canonical labeling (0 =
+ *           background; a component's pixels all hold 1 + the raster index
+ *           of its first pixel).  Not modified.
+ * out       DEVICE array of `capacity` records, caller-owned; record k is
+ *           the component with the k-th smallest label.  Only the first
+ *           `capacity` components are written (capacity 0: count only).
+ * n_out     DEVICE pointer to one u32: the number of components (all of
+ *           them, also beyond capacity).
+ * stream    hipStream_t; asynchronous like ccl_label_2d, and uses the same
+ *           per-stream workspace (about 0.2 bytes per pixel).
+ * Errors: CCL_ERR_INVALID_ARG (null pointers, H or W <= 0, capacity < 0),
+ * CCL_ERR_TOO_LARGE (H*W > 2^32-1), CCL_ERR_OUT_OF_MEMORY, CCL_ERR_HIP.
+ * Behaviour on a labeling that is not canonical is undefined.
+ */
+int ccl_component_stats(const uint32_t *labels, int32_t H, int32_t W, ccl_component *out,
+                        int64_t capacity, uint32_t *n_out, void *stream);
+
 /* ------------------------------------------------------------------ batch
  *
  * A context labels many images of different sizes in one call (the batched

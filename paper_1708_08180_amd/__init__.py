@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     autotune,
     label,
     label_batch,
+    component_stats,
     label_equal,
     label_plain,
     library_path,

@@ -68,6 +68,7 @@ SIGNATURES = {
     "ccl_label_2d_timed": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, ctypes.POINTER(Config), _P,
                                           ctypes.POINTER(ctypes.c_float)]),
     "ccl_label_2d_equal": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, ctypes.POINTER(Config), _P]),
+    "ccl_component_stats": (ctypes.c_int, [_P, _I32, _I32, _P, _I64, _P, _P]),
     "ccl_shutdown": (None, []),
     "ccl_ctx_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(CtxOpts)]),
     "ccl_ctx_destroy": (ctypes.c_int, [_P]),
@@ -243,6 +244,39 @@ def label_equal(img, conn: int = 8, out=None, config=None, stream=None):
                                     cfg, _stream_handle(stream))
     _check(rc, "ccl_label_2d_equal")
     return out
+
+
+# Layout of struct ccl_component (include/ccl.h).
+COMPONENT_DTYPE = [("label", "<u4"), ("area", "<u4"), ("x_min", "<u4"), ("y_min", "<u4"),
+                   ("x_max", "<u4"), ("y_max", "<u4"), ("sum_x", "<u8"), ("sum_y", "<u8")]
+COMPONENT_BYTES = 40
+
+
+def component_stats(labels, capacity: int = None, stream=None):
+    """Per-component statistics of a canonical label tensor (int32 CUDA,
+    H x W, from label / label_equal): a numpy structured array, one record
+    per component in increasing label order.  With capacity None the
+    components are counted first (one synchronization) and all returned."""
+    import numpy as np
+
+    torch = _torch()
+    if labels.dim() != 2 or labels.dtype != torch.int32 or not labels.is_contiguous():
+        raise ValueError("labels must be a contiguous 2D int32 CUDA tensor")
+    H, W = labels.shape
+    lib = load_library()
+    n_dev = torch.zeros(1, dtype=torch.int32, device=labels.device)
+    with torch.cuda.device(labels.device):
+        if capacity is None:
+            _check(lib.ccl_component_stats(labels.data_ptr(), H, W, None, 0, n_dev.data_ptr(),
+                                           _stream_handle(stream)), "ccl_component_stats")
+            capacity = int(n_dev.cpu().numpy().view(np.uint32)[0])
+        out = torch.empty(max(1, capacity) * COMPONENT_BYTES, dtype=torch.uint8, device=labels.device)
+        _check(lib.ccl_component_stats(labels.data_ptr(), H, W, out.data_ptr() if capacity else None,
+                                       int(capacity), n_dev.data_ptr(), _stream_handle(stream)),
+               "ccl_component_stats")
+    n = int(n_dev.cpu().numpy().view(np.uint32)[0])
+    rec = out.cpu().numpy()[:min(n, capacity) * COMPONENT_BYTES].view(np.dtype(COMPONENT_DTYPE))
+    return rec
 
 
 def label_timed(img, conn: int = 8, out=None, config=None, stream=None):

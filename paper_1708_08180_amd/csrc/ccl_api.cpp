@@ -28,6 +28,8 @@ struct WsEntry {
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, WsEntry> g_ws;
 
+}  // namespace
+
 // Workspace owned by the library for (current device, stream); grown on
 // demand.  Growth synchronizes the stream before releasing the old buffer
 // because earlier work on that stream may still read it.
@@ -57,8 +59,6 @@ int stream_workspace(hipStream_t s, size_t need, void **out) {
     *out = w.ptr;
     return CCL_OK;
 }
-
-}  // namespace
 
 void release_stream_workspaces() {
     std::lock_guard<std::mutex> lk(g_ws_mu);

@@ -62,6 +62,9 @@ inline WsLayout ws_layout(int H, int W, int th, bool equal = false) {
 
 // Shared by the entry points.
 int fail_hip(hipError_t e);
+// The library's workspace for (current device, stream), at least `need`
+// bytes (grown on demand; growth synchronizes the stream).
+int stream_workspace(hipStream_t s, size_t need, void **out);
 int validate_image(const void *img, int32_t H, int32_t W, int64_t pitch, const void *labels);
 int resolve_config(int H, int W, int conn, const ccl_config *cfg, int *th, int *nw);
 void default_config(int H, int W, int conn, int *th, int *nw);
