@@ -53,6 +53,10 @@ def _get():
             fn.restype = ctypes.c_int
             fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                            ctypes.c_int, ctypes.c_void_p]
+        lib.oracle_label_3d.restype = ctypes.c_int
+        lib.oracle_label_3d.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                        ctypes.c_void_p]
         lib.oracle_stats_2d.restype = ctypes.c_int
         lib.oracle_stats_2d.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
@@ -119,4 +123,18 @@ def stats(img: np.ndarray, conn: int = 8, equal: bool = False) -> np.ndarray:
                              out.ctypes.data if n.value else None, n.value, ctypes.byref(n))
     if rc != 0:
         raise ValueError("oracle_stats_2d failed with code %d" % rc)
+    return out
+
+
+def label3d(vol: np.ndarray, conn: int = 26) -> np.ndarray:
+    """Canonical 3D labels (conn 6, 18 or 26): 1 + the smallest raster index
+    z*H*W + y*W + x of each voxel's component, 0 for background."""
+    vol = np.ascontiguousarray(np.asarray(vol))
+    if vol.ndim != 3 or vol.dtype != np.uint8:
+        raise ValueError("expected a 3D uint8 volume")
+    D, H, W = vol.shape
+    out = np.empty((D, H, W), dtype=np.uint32)
+    rc = _get().oracle_label_3d(vol.ctypes.data, D, H, W, W, H * W, int(conn), out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_label_3d failed with code %d" % rc)
     return out

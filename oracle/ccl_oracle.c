@@ -180,3 +180,63 @@ int oracle_stats_2d(const uint8_t *img, int64_t H, int64_t W, int64_t pitch, int
     *n = count;
     return rc;
 }
+
+/* 3D labeling of a binary volume (D slices of H rows of W voxels; voxel
+ * (z, y, x) at vol[z * pitch_z + y * pitch_y + x], nonzero = foreground).
+ * Neighbours: conn 6 = the face neighbours, 18 = faces and edges, 26 =
+ * faces, edges and corners.  label = 1 + the smallest raster index
+ * z*H*W + y*W + x of the voxel's component, 0 for background; the same
+ * raster-order flood fill as in 2D. */
+int oracle_label_3d(const uint8_t *vol, int64_t D, int64_t H, int64_t W, int64_t pitch_y,
+                    int64_t pitch_z, int conn, uint32_t *out)
+{
+    if (!vol || !out || D <= 0 || H <= 0 || W <= 0 || pitch_y < W || pitch_z < H * pitch_y)
+        return ORACLE_EINVAL;
+    if (conn != 6 && conn != 18 && conn != 26)
+        return ORACLE_EINVAL;
+    const int64_t n = D * H * W;
+    if (n > (int64_t)0xFFFFFFFFll)
+        return ORACLE_EINVAL;
+    int dz[26], dy[26], dx[26], nnb = 0;
+    for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b)
+            for (int c = -1; c <= 1; ++c) {
+                const int steps = (a != 0) + (b != 0) + (c != 0);
+                if (steps == 0 || (conn == 6 && steps > 1) || (conn == 18 && steps > 2))
+                    continue;
+                dz[nnb] = a;
+                dy[nnb] = b;
+                dx[nnb] = c;
+                ++nnb;
+            }
+    int64_t *queue = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!queue)
+        return ORACLE_ENOMEM;
+    memset(out, 0, (size_t)n * sizeof(uint32_t));
+    const int64_t HW = H * W;
+    for (int64_t p = 0; p < n; ++p) {
+        const int64_t pz = p / HW, py = (p / W) % H, px = p % W;
+        if (out[p] != 0 || vol[pz * pitch_z + py * pitch_y + px] == 0)
+            continue;
+        const uint32_t lab = (uint32_t)(p + 1);
+        int64_t head = 0, tail = 0;
+        out[p] = lab;
+        queue[tail++] = p;
+        while (head < tail) {
+            const int64_t q = queue[head++];
+            const int64_t qz = q / HW, qy = (q / W) % H, qx = q % W;
+            for (int k = 0; k < nnb; ++k) {
+                const int64_t nz = qz + dz[k], ny = qy + dy[k], nx = qx + dx[k];
+                if (nz < 0 || nz >= D || ny < 0 || ny >= H || nx < 0 || nx >= W)
+                    continue;
+                const int64_t r = nz * HW + ny * W + nx;
+                if (out[r] != 0 || vol[nz * pitch_z + ny * pitch_y + nx] == 0)
+                    continue;
+                out[r] = lab;
+                queue[tail++] = r;
+            }
+        }
+    }
+    free(queue);
+    return ORACLE_OK;
+}
