@@ -233,9 +233,16 @@ def bench_serve(args, torch, log):
             "plain": plain_pts, "batched": batch_pts}
 
 
+def wl_rng(seed):
+    from paper_1708_08180_amd import workloads as wl
+
+    return wl.rng_for(seed)
+
+
 def bench_extensions(img, conn, torch, binding, reps=50):
-    """Equal-value labeling of the same image and per-component statistics
-    of its labels, event-timed on the work stream (parity is in the tests)."""
+    """Equal-value labeling of the same image, per-component statistics of
+    its labels and a 3D volume, event-timed on the work stream (parity is in
+    the tests)."""
     stream = torch.cuda.current_stream()
     d = torch.from_numpy(img).cuda()
     H, W = img.shape
@@ -262,8 +269,15 @@ def bench_extensions(img, conn, torch, binding, reps=50):
     sh = ctypes.c_void_p(stream.cuda_stream)
     ms_st = timed(lambda: lib.ccl_component_stats(lab.data_ptr(), H, W, recs.data_ptr(), n,
                                                   n_dev.data_ptr(), sh))
+    # 3D: 256^3 voxels, Bernoulli(0.3) (percolating under 26-connectivity)
+    vol_h = (wl_rng(2300).random((256, 256, 256)) < 0.3).astype("uint8")
+    vol = torch.from_numpy(vol_h).cuda()
+    lab3 = torch.empty(vol.shape, dtype=torch.int32, device="cuda")
+    ms_3d = timed(lambda: binding.label3d(vol, 26, out=lab3))
     px = H * W
-    return {"equal_value_labeling": {"ms": round(ms_eq, 5), "gpix_s": round(px / ms_eq / 1e6, 2),
+    return {"volume_3d": {"ms": round(ms_3d, 5), "gvox_s": round(vol_h.size / ms_3d / 1e6, 2),
+                          "note": "256^3 voxels Bernoulli(0.3) seed 2300, 26-connectivity"},
+            "equal_value_labeling": {"ms": round(ms_eq, 5), "gpix_s": round(px / ms_eq / 1e6, 2),
                                      "note": "every value class of the same image, background included"},
             "component_stats": {"ms": round(ms_st, 5), "components": n,
                                 "gpix_s": round(px / ms_st / 1e6, 2),

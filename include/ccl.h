@@ -184,6 +184,25 @@ typedef struct ccl_component {
 int ccl_component_stats(const uint32_t *labels, int32_t H, int32_t W, ccl_component *out,
                         int64_t capacity, uint32_t *n_out, void *stream);
 
+/*
+ * ccl_label_3d -- label a binary volume (the method on a 3D grid).
+ * vol     DEVICE, D slices of H rows of W voxels: voxel (z, y, x) at
+ *         vol[z * pitch_z + y * pitch_y + x]; nonzero = foreground.
+ *         pitch_y >= W, pitch_z >= H * pitch_y (bytes).
+ * connectivity  6 (face neighbours), 18 (faces and edges) or 26 (faces,
+ *         edges and corners).
+ * labels  DEVICE, dense D x H x W u32 (strides H*W and W), caller-owned;
+ *         labels[(z*H + y)*W + x] = 0 for background, else 1 + the smallest
+ *         raster index z'*H*W + y'*W + x' of the voxel's component.
+ *         Overwritten; also used as the union-find forest while the call
+ *         runs.  No workspace.
+ * Errors: CCL_ERR_INVALID_ARG (null pointers, sizes <= 0, pitches too
+ * small), CCL_ERR_UNSUPPORTED (connectivity), CCL_ERR_TOO_LARGE
+ * (D*H*W > 2^32-1), CCL_ERR_HIP.
+ */
+int ccl_label_3d(const uint8_t *vol, int32_t D, int32_t H, int32_t W, int64_t pitch_y,
+                 int64_t pitch_z, int32_t connectivity, uint32_t *labels, void *stream);
+
 /* ------------------------------------------------------------------ batch
  *
  * A context labels many images of different sizes in one call (the batched

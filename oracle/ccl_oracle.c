@@ -218,7 +218,7 @@ int oracle_label_3d(const uint8_t *vol, int64_t D, int64_t H, int64_t W, int64_t
         const int64_t pz = p / HW, py = (p / W) % H, px = p % W;
         if (out[p] != 0 || vol[pz * pitch_z + py * pitch_y + px] == 0)
             continue;
-        const uint32_t lab = (uint32_t)(p + 1);
+        const uint32_t lab = (uint32_t)p + 1u;
         int64_t head = 0, tail = 0;
         out[p] = lab;
         queue[tail++] = p;

@@ -14,6 +14,7 @@ from .binding import (  # noqa: F401
     label_batch,
     component_stats,
     label_equal,
+    label3d,
     label_plain,
     library_path,
     load_library,

@@ -69,6 +69,7 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_float)]),
     "ccl_label_2d_equal": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, ctypes.POINTER(Config), _P]),
     "ccl_component_stats": (ctypes.c_int, [_P, _I32, _I32, _P, _I64, _P, _P]),
+    "ccl_label_3d": (ctypes.c_int, [_P, _I32, _I32, _I32, _I64, _I64, _I32, _P, _P]),
     "ccl_shutdown": (None, []),
     "ccl_ctx_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(CtxOpts)]),
     "ccl_ctx_destroy": (ctypes.c_int, [_P]),
@@ -277,6 +278,28 @@ def component_stats(labels, capacity: int = None, stream=None):
     n = int(n_dev.cpu().numpy().view(np.uint32)[0])
     rec = out.cpu().numpy()[:min(n, capacity) * COMPONENT_BYTES].view(np.dtype(COMPONENT_DTYPE))
     return rec
+
+
+def label3d(vol, conn: int = 26, out=None, stream=None):
+    """Label a 3D uint8 CUDA tensor (D, H, W) with unit stride along W;
+    returns an int32 tensor of 1 + the smallest raster index of each voxel's
+    component (0 for background)."""
+    torch = _torch()
+    if vol.dim() != 3 or vol.dtype != torch.uint8 or not vol.is_cuda or vol.stride(2) != 1:
+        raise ValueError("vol must be a 3D uint8 CUDA tensor with unit stride along W")
+    D, H, W = vol.shape
+    if out is None:
+        out = torch.empty((D, H, W), dtype=torch.int32, device=vol.device)
+    elif tuple(out.shape) != (D, H, W) or out.dtype != torch.int32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor of shape (D, H, W)")
+    pitch_y = vol.stride(1) if H > 1 else W
+    pitch_z = vol.stride(0) if D > 1 else H * pitch_y
+    lib = load_library()
+    with torch.cuda.device(vol.device):
+        rc = lib.ccl_label_3d(vol.data_ptr(), D, H, W, pitch_y, pitch_z, int(conn), out.data_ptr(),
+                              _stream_handle(stream))
+    _check(rc, "ccl_label_3d")
+    return out
 
 
 def label_timed(img, conn: int = 8, out=None, config=None, stream=None):

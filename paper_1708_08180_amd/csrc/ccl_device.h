@@ -105,6 +105,19 @@ struct BatchArgs {
     uint32_t n, tiles;
 };
 
+// ---------------------------------------------------------- launch helpers
+
+// Consecutive workgroup ids are spread round-robin over the 8 XCDs; remap
+// them so that each XCD works on one contiguous run of tiles and
+// horizontally adjacent tiles (which share image cache lines) meet in the
+// same L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nb) {
+    constexpr uint32_t X = 8;
+    const uint32_t q = nb / X, r = nb % X;
+    const uint32_t xcd = bid % X, i = bid / X;
+    return xcd * q + (xcd < r ? xcd : r) + i;
+}
+
 // ------------------------------------------------------------------ helpers
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
@@ -444,15 +457,16 @@ __device__ __forceinline__ void sweep_band(uint32_t *par, uint8_t *col, const ui
     }
 }
 
-// Band seam of a multi-wavefront tile: the first row of band `wave` against
-// the last row of the band above, with general unions (any forest state).
+// Merge tile row r with an earlier tile row ru that touches it (the row
+// above for a band seam, the same row of the previous slice in 3D), with
+// general unions (any forest state).
 template <bool CONN8>
-__device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, int r) {
-    const uint64_t d = uniform64(msk[r]), u = uniform64(msk[r - 1]);
+__device__ __forceinline__ void merge_rows(uint32_t *par, const uint64_t *msk, int r, int ru) {
+    const uint64_t d = uniform64(msk[r]), u = uniform64(msk[ru]);
     const uint64_t S = run_starts(d), Su = run_starts(u);
     const bool isS = lane_in(S);
     const uint32_t node = (uint32_t)(r * kSlotsPerRow) + bits_below(S) - (isS ? 0u : 1u);
-    const uint32_t up = (uint32_t)((r - 1) * kSlotsPerRow);
+    const uint32_t up = (uint32_t)(ru * kSlotsPerRow);
     const uint32_t bu = bits_below(Su);
     const PairMasks p = pair_masks<CONN8>(d, u);
     if (CONN8) {
@@ -464,6 +478,13 @@ __device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, i
     } else {
         if (lane_in(p.pm)) lds_union(par, node, up + bu - (lane_in(Su) ? 0u : 1u));
     }
+}
+
+// Band seam of a multi-wavefront tile: the first row of band `wave` against
+// the last row of the band above.
+template <bool CONN8>
+__device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, int r) {
+    merge_rows<CONN8>(par, msk, r, r - 1);
 }
 
 // ------------------------------------------- equal-value labeling (K1 part)

@@ -24,17 +24,6 @@
 
 namespace ccl {
 
-// Consecutive workgroup ids are spread round-robin over the 8 XCDs; remap
-// them so that each XCD works on one contiguous run of tiles and
-// horizontally adjacent tiles (which share image cache lines) meet in the
-// same L2.
-__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nb) {
-    constexpr uint32_t X = 8;
-    const uint32_t q = nb / X, r = nb % X;
-    const uint32_t xcd = bid % X, i = bid / X;
-    return xcd * q + (xcd < r ? xcd : r) + i;
-}
-
 // ------------------------------------------------------------- local merge
 
 template <int TH, bool EQ>

@@ -1,0 +1,216 @@
+// 3D volume labeling (the paper's method on a 3D grid): the same three
+// phases over 3D tiles of 64 (x) x 16 (y) x 4 (z) voxels.
+//
+//   local merge   one wavefront per slice of the tile sweeps its 16 rows
+//                 with the 2D run union-find (4-connectivity inside a slice
+//                 for 6-connectivity, 8 for 18 and 26); then every row is
+//                 merged with the rows of the previous slice it touches
+//                 (general LDS unions over pair masks).  Every foreground
+//                 voxel gets labels[p] = 1 + its tile-local root (a dense
+//                 store, as in the paper's Kernel 1), which is already a
+//                 valid forest.
+//   boundary      every voxel on a tile face proposes its raster-earlier
+//                 neighbours that lie in another tile; requests are
+//                 deduplicated per wavefront and merged with the global
+//                 union-find of the 2D path.  Each pair of neighbours in
+//                 different tiles is proposed by its later voxel.
+//   link          every voxel is resolved to its root with full path
+//                 compression.
+#include <hip/hip_runtime.h>
+
+#include "ccl.h"
+#include "ccl_device.h"
+#include "ccl_internal.h"
+
+namespace ccl {
+
+namespace {
+
+constexpr int kTY = 16, kTZ = 4, kRows = kTY * kTZ;  // 64 tile rows
+
+struct Vol {
+    const uint8_t *vol;
+    uint32_t *labels;
+    int64_t pitch_y, pitch_z;
+    int32_t D, H, W;
+    int32_t tilesX, tilesY, tilesZ;
+    uint32_t n;
+    int32_t aligned16;
+};
+
+__device__ __forceinline__ uint4 load_chunk3d(const Vol &v, int x0, int y, int z, int q) {
+    uint4 b = make_uint4(0u, 0u, 0u, 0u);
+    if (y >= v.H || z >= v.D) return b;
+    const int x = x0 + q * 16;
+    const uint8_t *p = v.vol + (int64_t)z * v.pitch_z + (int64_t)y * v.pitch_y + x;
+    if (v.aligned16 && x + 16 <= v.W) return *(const uint4 *)p;
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        if (x + i < v.W) w[i >> 2] |= (uint32_t)p[i] << (8 * (i & 3));
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ __forceinline__ void tile_of(const Vol &v, uint32_t t, int &tx, int &ty, int &tz) {
+    const uint32_t TX = (uint32_t)v.tilesX, TY = (uint32_t)v.tilesY;
+    tx = (int)(t % TX);
+    ty = (int)((t / TX) % TY);
+    tz = (int)(t / (TX * TY));
+}
+
+template <int CONN>
+__global__ void __launch_bounds__(256) k1_local_merge3d(Vol v) {
+    constexpr bool CONN8 = CONN != 6;  // neighbours inside a slice
+    __shared__ uint32_t par[kRows * kSlotsPerRow];
+    __shared__ uint8_t col[kRows * kSlotsPerRow];
+    __shared__ uint64_t msk[kRows];
+    const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int tx, ty, tz;
+    tile_of(v, xcd_remap(blockIdx.x, gridDim.x), tx, ty, tz);
+    const int x0 = tx * kTileW, y0 = ty * kTY, z0 = tz * kTZ;
+    {
+        const int r = tid >> 2, q = tid & 3;  // 64 rows x 4 chunks, one per thread
+        ((uint16_t *)msk)[tid] =
+            (uint16_t)nonzero_bytes16(load_chunk3d(v, x0, y0 + (r % kTY), z0 + r / kTY, q));
+    }
+    __syncthreads();
+    // wavefront w sweeps slice w (rows w*16 .. w*16+15)
+    sweep_band<kRows, kTY, CONN8>(par, col, msk, wave, lane);
+    __syncthreads();
+    if (wave > 0) {
+        // rows of slice w against the rows of slice w-1 they touch
+        for (int yi = 0; yi < kTY; ++yi) {
+            const int r = wave * kTY + yi, ru = (wave - 1) * kTY + yi;
+            if (CONN == 6) {
+                merge_rows<false>(par, msk, r, ru);
+            } else {
+                merge_rows<true>(par, msk, r, ru);
+                // the rows above and below in the previous slice: straight
+                // (18: an edge neighbour) or with diagonals (26: corners too)
+                if (yi > 0) merge_rows<CONN == 26>(par, msk, r, ru - 1);
+                if (yi + 1 < kTY) merge_rows<CONN == 26>(par, msk, r, ru + 1);
+            }
+        }
+    }
+    __syncthreads();
+    // dense store: 1 + the global index of every foreground voxel's local root
+    const int x = x0 + lane;
+    for (int k = 0; k < kTY; ++k) {
+        const int r = wave * kTY + k;
+        const int y = y0 + k, z = z0 + wave;
+        if (y >= v.H || z >= v.D) break;  // wave-uniform
+        const uint64_t d = uniform64(msk[r]);
+        if (x >= v.W) continue;
+        uint32_t out = 0u;
+        if (lane_in(d)) {
+            const uint64_t S = run_starts(d);
+            const uint32_t node = (uint32_t)(r * kSlotsPerRow) + bits_below(S) - (lane_in(S) ? 0u : 1u);
+            const uint32_t root = lds_root(par, node);
+            const uint32_t rr = root / kSlotsPerRow;
+            const uint64_t g = ((uint64_t)(z0 + rr / kTY) * v.H + (uint64_t)(y0 + rr % kTY)) * v.W +
+                               (uint64_t)(x0 + col[root]);
+            out = (uint32_t)g + 1u;
+        }
+        v.labels[((uint64_t)z * v.H + y) * v.W + x] = out;
+    }
+}
+
+// Raster-earlier neighbour offsets (dz, dy, dx) for 26-connectivity; the
+// first `count` of them for each connectivity.
+struct Off { int8_t dz, dy, dx, steps; };
+__constant__ Off kBack[13] = {
+    {0, 0, -1, 1}, {0, -1, 0, 1}, {-1, 0, 0, 1},                                     // faces
+    {0, -1, -1, 2}, {0, -1, 1, 2}, {-1, 0, -1, 2}, {-1, 0, 1, 2}, {-1, -1, 0, 2},
+    {-1, 1, 0, 2},                                                                   // edges
+    {-1, -1, -1, 3}, {-1, -1, 1, 3}, {-1, 1, -1, 3}, {-1, 1, 1, 3}};                 // corners
+
+template <int CONN>
+__global__ void __launch_bounds__(256) k2_boundary3d(Vol v, uint32_t rows_total) {
+    constexpr int NOFF = CONN == 6 ? 3 : (CONN == 18 ? 9 : 13);
+    // one wavefront per tile row (tile t, row r = slice * 16 + y)
+    const uint32_t wrow = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4u + (threadIdx.x >> 6)));
+    if (wrow >= rows_total) return;
+    const uint32_t t = wrow / kRows;
+    const int r = (int)(wrow % kRows);
+    int tx, ty, tz;
+    tile_of(v, t, tx, ty, tz);
+    const int lane = lane_id();
+    const int x0 = tx * kTileW, y0 = ty * kTY, z0 = tz * kTZ;
+    const int x = x0 + lane, y = y0 + r % kTY, z = z0 + r / kTY;
+    if (y >= v.H || z >= v.D) return;  // wave-uniform
+    const bool in = x < v.W;
+    const uint32_t *L = v.labels;
+    const uint64_t HW = (uint64_t)v.H * v.W;
+    const uint32_t lp = in ? L[(uint64_t)z * HW + (uint64_t)y * v.W + x] : 0u;
+    // rows inside the tile's box in y and z reach other tiles only sideways
+    const bool faceZ = z == z0, faceY = y == y0 || y == y0 + kTY - 1;
+#pragma unroll
+    for (int o = 0; o < NOFF; ++o) {
+        const Off d = kBack[o];
+        if (!faceZ && !faceY && d.dx == 0) continue;  // wave-uniform: stays inside the tile
+        const int qz = z + d.dz, qy = y + d.dy, qx = x + d.dx;
+        const bool outside = qz < z0 || qy < y0 || qy >= y0 + kTY || qx < x0 || qx >= x0 + kTileW;
+        const bool valid = lp != 0u && outside && qz >= 0 && qy >= 0 && qy < v.H && qx >= 0 && qx < v.W;
+        uint32_t lq = 0u;
+        if (valid) lq = L[(uint64_t)qz * HW + (uint64_t)qy * v.W + (uint64_t)qx];
+        uint32_t A[1] = {lp - 1u}, B[1] = {lq != 0u ? lq - 1u : kNone};
+        union_requests<1>(v.labels, v.n, A, B);
+    }
+}
+
+__global__ void __launch_bounds__(256) k3_link3d(uint32_t *L, uint32_t n) {
+    const uint64_t p = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    if (p >= n) return;
+    if (L[p] != 0u) (void)g_find_final(L, (uint32_t)p);
+}
+
+}  // namespace
+
+}  // namespace ccl
+
+using namespace ccl;
+
+extern "C" int ccl_label_3d(const uint8_t *vol, int32_t D, int32_t H, int32_t W, int64_t pitch_y,
+                            int64_t pitch_z, int32_t connectivity, uint32_t *labels, void *stream) {
+    if (!vol || !labels || D <= 0 || H <= 0 || W <= 0) return CCL_ERR_INVALID_ARG;
+    if (pitch_y < (int64_t)W || pitch_z < (int64_t)H * pitch_y) return CCL_ERR_INVALID_ARG;
+    if (connectivity != 6 && connectivity != 18 && connectivity != 26) return CCL_ERR_UNSUPPORTED;
+    const uint64_t n = (uint64_t)D * (uint64_t)H * (uint64_t)W;
+    if (n > 0xFFFFFFFFull) return CCL_ERR_TOO_LARGE;
+    Vol v;
+    v.vol = vol;
+    v.labels = labels;
+    v.pitch_y = pitch_y;
+    v.pitch_z = pitch_z;
+    v.D = D;
+    v.H = H;
+    v.W = W;
+    v.tilesX = (W + kTileW - 1) / kTileW;
+    v.tilesY = (H + kTY - 1) / kTY;
+    v.tilesZ = (D + kTZ - 1) / kTZ;
+    v.n = (uint32_t)n;
+    v.aligned16 = (((uintptr_t)vol & 15u) == 0 && (pitch_y & 15) == 0 && (pitch_z & 15) == 0) ? 1 : 0;
+    const uint64_t tiles = (uint64_t)v.tilesX * v.tilesY * v.tilesZ;
+    if (tiles * kRows > 0x7FFFFFFFull) return CCL_ERR_TOO_LARGE;
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t rows = (uint32_t)(tiles * kRows);
+    switch (connectivity) {
+        case 6:
+            hipLaunchKernelGGL(k1_local_merge3d<6>, dim3((uint32_t)tiles), dim3(256), 0, s, v);
+            hipLaunchKernelGGL(k2_boundary3d<6>, dim3((rows + 3) / 4), dim3(256), 0, s, v, rows);
+            break;
+        case 18:
+            hipLaunchKernelGGL(k1_local_merge3d<18>, dim3((uint32_t)tiles), dim3(256), 0, s, v);
+            hipLaunchKernelGGL(k2_boundary3d<18>, dim3((rows + 3) / 4), dim3(256), 0, s, v, rows);
+            break;
+        default:
+            hipLaunchKernelGGL(k1_local_merge3d<26>, dim3((uint32_t)tiles), dim3(256), 0, s, v);
+            hipLaunchKernelGGL(k2_boundary3d<26>, dim3((rows + 3) / 4), dim3(256), 0, s, v, rows);
+            break;
+    }
+    hipLaunchKernelGGL(k3_link3d, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, labels,
+                       (uint32_t)n);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e);
+    return CCL_OK;
+}

@@ -77,6 +77,19 @@ def test_equal_config_validation():
         assert lib.ccl_label_2d_equal(FAKE, 64, 64, 64, 8, FAKE, ctypes.byref(cfg), None) == 2
 
 
+@pytest.mark.parametrize("args,code", [
+    ((None, 2, 4, 4, 4, 16, 26, FAKE, None), 1),          # null volume
+    ((FAKE, 0, 4, 4, 4, 16, 26, FAKE, None), 1),          # D = 0
+    ((FAKE, 2, 4, 8, 7, 32, 26, FAKE, None), 1),          # pitch_y < W
+    ((FAKE, 2, 4, 8, 8, 31, 26, FAKE, None), 1),          # pitch_z < H * pitch_y
+    ((FAKE, 2, 4, 4, 4, 16, 8, FAKE, None), 2),           # connectivity 8
+    ((FAKE, 2048, 2048, 2048, 2048, 2048 * 2048, 6, FAKE, None), 3),  # D*H*W > 2^32-1
+])
+def test_3d_invalid_arguments(args, code):
+    lib = binding.load_library()
+    assert lib.ccl_label_3d(*args) == code
+
+
 def test_ex_validation():
     lib = binding.load_library()
     cfg = binding.Config(48, 4)
