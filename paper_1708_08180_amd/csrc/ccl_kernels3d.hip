@@ -10,10 +10,10 @@
 //                 store, as in the paper's Kernel 1), which is already a
 //                 valid forest.
 //   boundary      every voxel on a tile face proposes its raster-earlier
-//                 neighbours that lie in another tile; requests are
-//                 deduplicated per wavefront and merged with the global
-//                 union-find of the 2D path.  Each pair of neighbours in
-//                 different tiles is proposed by its later voxel.
+//                 neighbours that lie in another tile (each such pair is
+//                 proposed by its later voxel, once); requests are
+//                 deduplicated along a face and merged with the global
+//                 union-find of the 2D path.
 //   link          every voxel is resolved to its root with full path
 //                 compression.
 #include <hip/hip_runtime.h>
@@ -93,6 +93,14 @@ __global__ void __launch_bounds__(256) k1_local_merge3d(Vol v) {
         }
     }
     __syncthreads();
+    // every run node finds its root (read-only walk); its owner alone stores
+    // it, so par[] is one step from the root afterwards
+    for (int n = tid; n < kRows * kSlotsPerRow; n += 256) {
+        if ((n % kSlotsPerRow) >= __popcll(run_starts(msk[n / kSlotsPerRow]))) continue;
+        const uint32_t root = lds_root(par, (uint32_t)n);
+        if (root != (uint32_t)n) lds_st(&par[n], root);
+    }
+    __syncthreads();
     // dense store: 1 + the global index of every foreground voxel's local root
     const int x = x0 + lane;
     for (int k = 0; k < kTY; ++k) {
@@ -105,7 +113,7 @@ __global__ void __launch_bounds__(256) k1_local_merge3d(Vol v) {
         if (lane_in(d)) {
             const uint64_t S = run_starts(d);
             const uint32_t node = (uint32_t)(r * kSlotsPerRow) + bits_below(S) - (lane_in(S) ? 0u : 1u);
-            const uint32_t root = lds_root(par, node);
+            const uint32_t root = lds_ld(&par[node]);
             const uint32_t rr = root / kSlotsPerRow;
             const uint64_t g = ((uint64_t)(z0 + rr / kTY) * v.H + (uint64_t)(y0 + rr % kTY)) * v.W +
                                (uint64_t)(x0 + col[root]);
@@ -124,37 +132,58 @@ __constant__ Off kBack[13] = {
     {-1, 1, 0, 2},                                                                   // edges
     {-1, -1, -1, 3}, {-1, -1, 1, 3}, {-1, 1, -1, 3}, {-1, 1, 1, 3}};                 // corners
 
+// Boundary analysis of tile t.  A pair of neighbours in different tiles is
+// proposed by its raster-later voxel p.  The candidates are split so that
+// every pair is seen once and requests along a face are deduplicated across
+// a whole wavefront:
+//   x-lines (lane = column): the 22 tile rows on the front face (first
+//     slice) or on the top / bottom row of a slice, for the neighbours that
+//     leave the tile through y or z;
+//   x-faces (lane = tile row): the first and the last column of the tile,
+//     for the neighbours that leave it through x only.
 template <int CONN>
-__global__ void __launch_bounds__(256) k2_boundary3d(Vol v, uint32_t rows_total) {
+__global__ void __launch_bounds__(256) k2_boundary3d(Vol v) {
     constexpr int NOFF = CONN == 6 ? 3 : (CONN == 18 ? 9 : 13);
-    // one wavefront per tile row (tile t, row r = slice * 16 + y)
-    const uint32_t wrow = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4u + (threadIdx.x >> 6)));
-    if (wrow >= rows_total) return;
-    const uint32_t t = wrow / kRows;
-    const int r = (int)(wrow % kRows);
+    constexpr int kLines = kTY + 2 * (kTZ - 1);  // 22 x-lines per tile
     int tx, ty, tz;
-    tile_of(v, t, tx, ty, tz);
+    tile_of(v, blockIdx.x, tx, ty, tz);
     const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
     const int x0 = tx * kTileW, y0 = ty * kTY, z0 = tz * kTZ;
-    const int x = x0 + lane, y = y0 + r % kTY, z = z0 + r / kTY;
-    if (y >= v.H || z >= v.D) return;  // wave-uniform
-    const bool in = x < v.W;
     const uint32_t *L = v.labels;
     const uint64_t HW = (uint64_t)v.H * v.W;
-    const uint32_t lp = in ? L[(uint64_t)z * HW + (uint64_t)y * v.W + x] : 0u;
-    // rows inside the tile's box in y and z reach other tiles only sideways
-    const bool faceZ = z == z0, faceY = y == y0 || y == y0 + kTY - 1;
+    auto at = [&](int z, int y, int x) { return L[(uint64_t)z * HW + (uint64_t)y * v.W + (uint64_t)x]; };
+    for (int task = wave; task < kLines + 2; task += 4) {
+        int z, y, x;
+        bool xface;
+        if (task < kLines) {
+            // rows 0..15: the first slice; then the top and bottom rows of slices 1..3
+            const int r = task < kTY ? task : (task - kTY) / 2 * kTY + kTY + ((task - kTY) & 1) * (kTY - 1);
+            z = z0 + r / kTY;
+            y = y0 + r % kTY;
+            x = x0 + lane;
+            xface = false;
+        } else {
+            z = z0 + lane / kTY;
+            y = y0 + lane % kTY;
+            x = task == kLines ? x0 : x0 + kTileW - 1;
+            xface = true;
+        }
+        const bool in = z < v.D && y < v.H && x < v.W;
+        const uint32_t lp = in ? at(z, y, x) : 0u;
 #pragma unroll
-    for (int o = 0; o < NOFF; ++o) {
-        const Off d = kBack[o];
-        if (!faceZ && !faceY && d.dx == 0) continue;  // wave-uniform: stays inside the tile
-        const int qz = z + d.dz, qy = y + d.dy, qx = x + d.dx;
-        const bool outside = qz < z0 || qy < y0 || qy >= y0 + kTY || qx < x0 || qx >= x0 + kTileW;
-        const bool valid = lp != 0u && outside && qz >= 0 && qy >= 0 && qy < v.H && qx >= 0 && qx < v.W;
-        uint32_t lq = 0u;
-        if (valid) lq = L[(uint64_t)qz * HW + (uint64_t)qy * v.W + (uint64_t)qx];
-        uint32_t A[1] = {lp - 1u}, B[1] = {lq != 0u ? lq - 1u : kNone};
-        union_requests<1>(v.labels, v.n, A, B);
+        for (int o = 0; o < NOFF; ++o) {
+            const Off d = kBack[o];
+            if (xface && d.dx != (task == kLines ? -1 : 1)) continue;  // wave-uniform
+            const int qz = z + d.dz, qy = y + d.dy, qx = x + d.dx;
+            const bool outYZ = qz < z0 || qy < y0 || qy >= y0 + kTY;
+            const bool outX = qx < x0 || qx >= x0 + kTileW;
+            const bool mine = xface ? (outX && !outYZ) : outYZ;
+            const bool valid = lp != 0u && mine && qz >= 0 && qy >= 0 && qy < v.H && qx >= 0 && qx < v.W;
+            const uint32_t lq = valid ? at(qz, qy, qx) : 0u;
+            uint32_t A[1] = {lp - 1u}, B[1] = {lq != 0u ? lq - 1u : kNone};
+            union_requests<1>(v.labels, v.n, A, B);
+        }
     }
 }
 
@@ -193,19 +222,18 @@ extern "C" int ccl_label_3d(const uint8_t *vol, int32_t D, int32_t H, int32_t W,
     const uint64_t tiles = (uint64_t)v.tilesX * v.tilesY * v.tilesZ;
     if (tiles * kRows > 0x7FFFFFFFull) return CCL_ERR_TOO_LARGE;
     hipStream_t s = (hipStream_t)stream;
-    const uint32_t rows = (uint32_t)(tiles * kRows);
     switch (connectivity) {
         case 6:
             hipLaunchKernelGGL(k1_local_merge3d<6>, dim3((uint32_t)tiles), dim3(256), 0, s, v);
-            hipLaunchKernelGGL(k2_boundary3d<6>, dim3((rows + 3) / 4), dim3(256), 0, s, v, rows);
+            hipLaunchKernelGGL(k2_boundary3d<6>, dim3((uint32_t)tiles), dim3(256), 0, s, v);
             break;
         case 18:
             hipLaunchKernelGGL(k1_local_merge3d<18>, dim3((uint32_t)tiles), dim3(256), 0, s, v);
-            hipLaunchKernelGGL(k2_boundary3d<18>, dim3((rows + 3) / 4), dim3(256), 0, s, v, rows);
+            hipLaunchKernelGGL(k2_boundary3d<18>, dim3((uint32_t)tiles), dim3(256), 0, s, v);
             break;
         default:
             hipLaunchKernelGGL(k1_local_merge3d<26>, dim3((uint32_t)tiles), dim3(256), 0, s, v);
-            hipLaunchKernelGGL(k2_boundary3d<26>, dim3((rows + 3) / 4), dim3(256), 0, s, v, rows);
+            hipLaunchKernelGGL(k2_boundary3d<26>, dim3((uint32_t)tiles), dim3(256), 0, s, v);
             break;
     }
     hipLaunchKernelGGL(k3_link3d, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, labels,

@@ -13,9 +13,10 @@
 //                of every word, and the records of its roots initialised;
 //   st_accum     every run of equal labels in a row adds its length,
 //                extent and coordinate sums to its component's record: first
-//                into a hash table in LDS per 64 x 64 block (a large
-//                component has thousands of runs, which would otherwise all
-//                hit one record), then with global atomics.
+//                into a hash table in LDS keyed by label per 64 x 256 block
+//                (a large component has thousands of runs, which would
+//                otherwise all hit one record), then once per table slot
+//                with global atomics.
 #include <hip/hip_runtime.h>
 
 #include "ccl.h"
@@ -27,7 +28,6 @@ namespace ccl {
 namespace {
 
 constexpr int kWordsPerBlock = 64;
-constexpr int kHashSlots = 512;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
 __global__ void __launch_bounds__(256) st_roots(const uint32_t *L, uint32_t W, uint32_t WW,
@@ -113,31 +113,41 @@ __global__ void __launch_bounds__(64) st_bases(const uint64_t *mask, const uint3
     }
 }
 
-struct RunAdd {
-    uint32_t len, x0, x1, y;
-    uint64_t sx, sy;
-};
-
-__device__ __forceinline__ void add_global(ccl_component *out, uint32_t id, const RunAdd &a) {
-    ccl_component &r = out[id];
-    atomicAdd(&r.area, a.len);
-    atomicMin(&r.x_min, a.x0);
-    atomicMax(&r.x_max, a.x1);
-    atomicMin(&r.y_min, a.y);
-    atomicMax(&r.y_max, a.y);
-    atomicAdd((unsigned long long *)&r.sum_x, (unsigned long long)a.sx);
-    atomicAdd((unsigned long long *)&r.sum_y, (unsigned long long)a.sy);
+__device__ __forceinline__ void add_global(ccl_component &r, uint32_t len, uint32_t xmn, uint32_t xmx,
+                                           uint32_t ymn, uint32_t ymx, uint64_t sxv, uint64_t syv) {
+    atomicAdd(&r.area, len);
+    atomicMin(&r.x_min, xmn);
+    atomicMax(&r.x_max, xmx);
+    atomicMin(&r.y_min, ymn);
+    atomicMax(&r.y_max, ymx);
+    atomicAdd((unsigned long long *)&r.sum_x, (unsigned long long)sxv);
+    atomicAdd((unsigned long long *)&r.sum_y, (unsigned long long)syv);
 }
 
-__global__ void __launch_bounds__(256) st_accum(const uint32_t *L, uint32_t H, uint32_t W,
-                                                 uint32_t WW, const uint64_t *mask,
-                                                 const uint32_t *base, ccl_component *out,
-                                                 uint32_t cap) {
-    __shared__ uint32_t key[kHashSlots], area[kHashSlots], xmn[kHashSlots], ymn[kHashSlots],
-        xmx[kHashSlots], ymx[kHashSlots];
-    __shared__ unsigned long long sx[kHashSlots], sy[kHashSlots];
+// Record index of the component whose root pixel is r (its label - 1).
+__device__ __forceinline__ uint32_t record_of(uint32_t r, uint32_t W, uint32_t WW,
+                                              const uint64_t *mask, const uint32_t *base) {
+    const uint32_t rx = r % W;
+    const uint32_t w = (r / W) * WW + rx / (uint32_t)kTileW;
+    return base[w] + (uint32_t)__popcll(mask[w] & ((1ull << (rx & 63u)) - 1ull));
+}
+
+// Block of 64 columns x kAccRows rows, 16 wavefronts of 16 rows each.  The
+// hash table is keyed by label, so a run needs no global read; the record
+// index is looked up once per table slot when the block flushes.
+constexpr int kAccWaves = 16, kAccRowsPerWave = 16, kAccRows = kAccWaves * kAccRowsPerWave;
+constexpr int kAccSlots = 1024;
+
+__global__ void __launch_bounds__(kAccWaves * 64) st_accum(const uint32_t *L, uint32_t H, uint32_t W,
+                                                          uint32_t WW, const uint64_t *mask,
+                                                          const uint32_t *base, ccl_component *out,
+                                                          uint32_t cap) {
+    __shared__ uint32_t key[kAccSlots], area[kAccSlots], xmn[kAccSlots], ymn[kAccSlots],
+        xmx[kAccSlots], ymx[kAccSlots];
+    __shared__ unsigned long long sx[kAccSlots], sy[kAccSlots];
+    constexpr int NT = kAccWaves * 64;
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = tid; i < kHashSlots; i += 256) {
+    for (int i = tid; i < kAccSlots; i += NT) {
         key[i] = kEmpty;
         area[i] = 0u;
         xmn[i] = ymn[i] = 0xFFFFFFFFu;
@@ -145,12 +155,12 @@ __global__ void __launch_bounds__(256) st_accum(const uint32_t *L, uint32_t H, u
         sx[i] = sy[i] = 0ull;
     }
     __syncthreads();
-    const uint32_t x0 = blockIdx.x * (uint32_t)kTileW, y0 = blockIdx.y * 64u;
+    const uint32_t x0 = blockIdx.x * (uint32_t)kTileW, y0 = blockIdx.y * (uint32_t)kAccRows;
     const uint32_t n = H * W;
     const uint32_t x = x0 + (uint32_t)lane;
     const bool xin = x < W;
-    for (int k = 0; k < 16; ++k) {
-        const uint32_t y = y0 + (uint32_t)(wave * 16 + k);
+    for (int k = 0; k < kAccRowsPerWave; ++k) {
+        const uint32_t y = y0 + (uint32_t)(wave * kAccRowsPerWave + k);
         if (y >= H) break;  // wave-uniform
         const uint32_t l = xin ? L[y * W + x] : 0u;
         const uint32_t ll = from_left(l, 0u), lr = from_right(l, 0u);
@@ -160,49 +170,37 @@ __global__ void __launch_bounds__(256) st_accum(const uint32_t *L, uint32_t H, u
         // this lane starts a run of equal labels; it ends at the first run
         // end at or after it
         const uint32_t e = (uint32_t)lane + (uint32_t)__builtin_ctzll(E >> lane);
-        RunAdd a;
-        a.len = e - (uint32_t)lane + 1u;
-        a.x0 = x;
-        a.x1 = x0 + e;
-        a.y = y;
-        a.sx = (uint64_t)a.len * ((uint64_t)a.x0 + (uint64_t)a.x1) / 2u;
-        a.sy = (uint64_t)a.len * (uint64_t)y;
-        const uint32_t r = l - 1u;
-        const uint32_t rx = r % W;
-        const uint32_t w = (r / W) * WW + rx / (uint32_t)kTileW;
-        const uint32_t id = base[w] + (uint32_t)__popcll(mask[w] & ((1ull << (rx & 63u)) - 1ull));
-        if (id >= cap) continue;
-        uint32_t h = (id * 2654435761u) >> 23;
+        const uint32_t len = e - (uint32_t)lane + 1u, x1 = x0 + e;
+        const uint64_t sxv = (uint64_t)len * ((uint64_t)x + (uint64_t)x1) / 2u;
+        const uint64_t syv = (uint64_t)len * (uint64_t)y;
+        uint32_t h = (l * 2654435761u) >> 22;  // 10 bits
         bool done = false;
         for (int probe = 0; probe < 16 && !done; ++probe) {
-            const uint32_t kk = atomicCAS(&key[h], kEmpty, id);
-            if (kk == kEmpty || kk == id) {
-                atomicAdd(&area[h], a.len);
-                atomicMin(&xmn[h], a.x0);
-                atomicMax(&xmx[h], a.x1);
-                atomicMin(&ymn[h], a.y);
-                atomicMax(&ymx[h], a.y);
-                atomicAdd(&sx[h], (unsigned long long)a.sx);
-                atomicAdd(&sy[h], (unsigned long long)a.sy);
+            const uint32_t kk = atomicCAS(&key[h], kEmpty, l);
+            if (kk == kEmpty || kk == l) {
+                atomicAdd(&area[h], len);
+                atomicMin(&xmn[h], x);
+                atomicMax(&xmx[h], x1);
+                atomicMin(&ymn[h], y);
+                atomicMax(&ymx[h], y);
+                atomicAdd(&sx[h], (unsigned long long)sxv);
+                atomicAdd(&sy[h], (unsigned long long)syv);
                 done = true;
             } else {
-                h = (h + 1u) & (uint32_t)(kHashSlots - 1);
+                h = (h + 1u) & (uint32_t)(kAccSlots - 1);
             }
         }
-        if (!done) add_global(out, id, a);  // table full around h: straight to the record
+        if (!done) {  // table full around h: straight to the record
+            const uint32_t id = record_of(l - 1u, W, WW, mask, base);
+            if (id < cap) add_global(out[id], len, x, x1, y, y, sxv, syv);
+        }
     }
     __syncthreads();
-    for (int i = tid; i < kHashSlots; i += 256) {
-        const uint32_t id = key[i];
-        if (id == kEmpty) continue;
-        ccl_component &r = out[id];
-        atomicAdd(&r.area, area[i]);
-        atomicMin(&r.x_min, xmn[i]);
-        atomicMax(&r.x_max, xmx[i]);
-        atomicMin(&r.y_min, ymn[i]);
-        atomicMax(&r.y_max, ymx[i]);
-        atomicAdd((unsigned long long *)&r.sum_x, sx[i]);
-        atomicAdd((unsigned long long *)&r.sum_y, sy[i]);
+    for (int i = tid; i < kAccSlots; i += NT) {
+        const uint32_t l = key[i];
+        if (l == kEmpty) continue;
+        const uint32_t id = record_of(l - 1u, W, WW, mask, base);
+        if (id < cap) add_global(out[id], area[i], xmn[i], xmx[i], ymn[i], ymx[i], sx[i], sy[i]);
     }
 }
 
@@ -242,7 +240,8 @@ extern "C" int ccl_component_stats(const uint32_t *labels, int32_t H, int32_t W,
     hipLaunchKernelGGL(st_scan, dim3(1), dim3(1024), 0, s, bsum, nb, n_out);
     hipLaunchKernelGGL(st_bases, dim3(nb), dim3(64), 0, s, mask, bsum, words, (uint32_t)W, WW, base,
                        out, cap);
-    hipLaunchKernelGGL(st_accum, dim3(WW, ((uint32_t)H + 63u) / 64u), dim3(256), 0, s, labels,
+    hipLaunchKernelGGL(st_accum, dim3(WW, ((uint32_t)H + kAccRows - 1u) / kAccRows), dim3(kAccWaves * 64),
+                       0, s, labels,
                        (uint32_t)H, (uint32_t)W, WW, mask, base, out, cap);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail_hip(e);
