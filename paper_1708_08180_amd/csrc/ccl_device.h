@@ -21,9 +21,10 @@
 //                   masks (boundary analysis)
 //   roots[...]      global raster index of the tile-local root of every cell
 //                   on those four edges (boundary analysis)
-//   rowmask[2*TH]   the 64-bit foreground mask of every tile row, then per
+//   rowmask[...]    the 64-bit foreground mask of every tile row, then per
 //                   row the mask of the local root pixels whose component
-//                   touches a shared tile edge (link)
+//                   touches a shared tile edge, then every row's first run
+//                   record (16 bits each) (link)
 //   slots[TH][32]   per row, one 16-bit record per run in left-to-right
 //                   order: the tile-local pixel index of the run's local
 //                   root (link)
@@ -48,6 +49,9 @@ __host__ __device__ constexpr int slots_per_row() { return EQ ? 64 : 32; }
 constexpr int kSlotsPerRow = slots_per_row<false>();
 
 __host__ __device__ constexpr int roots_per_tile(int th) { return 2 * kTileW + 2 * th; }
+// 64-bit words per tile of the row data: TH row masks, TH edge-root masks,
+// then TH 16-bit row bases (first record of every row)
+__host__ __device__ constexpr int rowmask_words(int th) { return 2 * th + th / 4; }
 __host__ __device__ constexpr int roots_top(int) { return 0; }
 __host__ __device__ constexpr int roots_bottom(int) { return kTileW; }
 __host__ __device__ constexpr int roots_left(int) { return 2 * kTileW; }
@@ -59,7 +63,7 @@ struct ImgView {
     uint32_t *labels;
     uint64_t *masks;    // [tiles][4]
     uint32_t *roots;    // [tiles][roots_per_tile(TH)]
-    uint64_t *rowmask;  // [tiles][2*TH]: row masks, then edge-root masks
+    uint64_t *rowmask;  // [tiles][rowmask_words(TH)]: row masks, edge-root masks, row bases
     uint16_t *slots;    // [tiles][TH][slots_per_row]
     int64_t pitch;
     int32_t H, W;
@@ -370,6 +374,20 @@ __device__ __forceinline__ uint32_t from_right(uint32_t v, uint32_t edge) {
 
 __device__ __forceinline__ uint64_t run_starts(uint64_t d) { return d & ~(d << 1); }
 
+// Exclusive prefix sum over the 64 lanes of a wavefront; *total gets the
+// sum of all lanes.
+__device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t x, uint32_t *total) {
+    const int lane = (int)(threadIdx.x & 63);
+    uint32_t incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    *total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    return incl - x;
+}
+
 // A value every lane holds identically, moved to scalar registers.
 __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
@@ -414,9 +432,14 @@ __device__ __forceinline__ PairMasks pair_masks(uint64_t d, uint64_t u, uint64_t
 // atomicMin per lane on its node); every other root it touches is joined
 // to that one by a real union, which is rare.  Only after a row that had one
 // are the row's roots re-resolved, so `ra` always holds true roots.
+//
+// Node numbering: the first node of tile row j is lane j's value of `rbv`
+// (a row's nodes are consecutive and rows follow each other, so nodes stay
+// in raster order of run starts): either dense, an exclusive scan of the
+// rows' run counts, or sparse, j * 32.  cr[node] = first column | row << 8.
 template <int TH, int RPW, bool CONN8>
-__device__ __forceinline__ void sweep_band(uint32_t *par, uint8_t *col, const uint64_t *msk,
-                                           int wave, int lane) {
+__device__ __forceinline__ void sweep_band(uint32_t *par, uint16_t *cr, const uint64_t *msk,
+                                           int wave, int lane, uint32_t rbv) {
     uint32_t ra = kNone;
     uint64_t u = 0;
     uint64_t m[RPW];
@@ -428,11 +451,12 @@ __device__ __forceinline__ void sweep_band(uint32_t *par, uint8_t *col, const ui
         const uint64_t d = m[k];
         const uint64_t S = run_starts(d);
         const bool fg = lane_in(d), isS = lane_in(S);
-        const uint32_t node = (uint32_t)(r * kSlotsPerRow) + bits_below(S) - (isS ? 0u : 1u);
+        const uint32_t rb = (uint32_t)__builtin_amdgcn_readlane((int)rbv, r);
+        const uint32_t node = rb + bits_below(S) - (isS ? 0u : 1u);
         uint32_t *pn = &par[node];
         if (isS) {
             lds_st(pn, node);
-            col[node] = (uint8_t)lane;
+            cr[node] = (uint16_t)(lane | (r << 8));
         }
         uint32_t md = fg ? node : kNone;
         if (k > 0) {
@@ -460,13 +484,15 @@ __device__ __forceinline__ void sweep_band(uint32_t *par, uint8_t *col, const ui
 // Merge tile row r with an earlier tile row ru that touches it (the row
 // above for a band seam, the same row of the previous slice in 3D), with
 // general unions (any forest state).
+// `base` / `base_u`: first node of row r / ru.
 template <bool CONN8>
-__device__ __forceinline__ void merge_rows(uint32_t *par, const uint64_t *msk, int r, int ru) {
+__device__ __forceinline__ void merge_rows(uint32_t *par, const uint64_t *msk, int r, int ru,
+                                           uint32_t base, uint32_t base_u) {
     const uint64_t d = uniform64(msk[r]), u = uniform64(msk[ru]);
     const uint64_t S = run_starts(d), Su = run_starts(u);
     const bool isS = lane_in(S);
-    const uint32_t node = (uint32_t)(r * kSlotsPerRow) + bits_below(S) - (isS ? 0u : 1u);
-    const uint32_t up = (uint32_t)(ru * kSlotsPerRow);
+    const uint32_t node = base + bits_below(S) - (isS ? 0u : 1u);
+    const uint32_t up = base_u;
     const uint32_t bu = bits_below(Su);
     const PairMasks p = pair_masks<CONN8>(d, u);
     if (CONN8) {
@@ -483,8 +509,9 @@ __device__ __forceinline__ void merge_rows(uint32_t *par, const uint64_t *msk, i
 // Band seam of a multi-wavefront tile: the first row of band `wave` against
 // the last row of the band above.
 template <bool CONN8>
-__device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, int r) {
-    merge_rows<CONN8>(par, msk, r, r - 1);
+__device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, int r, uint32_t rbv) {
+    merge_rows<CONN8>(par, msk, r, r - 1, (uint32_t)__builtin_amdgcn_readlane((int)rbv, r),
+                      (uint32_t)__builtin_amdgcn_readlane((int)rbv, r - 1));
 }
 
 // ------------------------------------------- equal-value labeling (K1 part)
@@ -502,7 +529,7 @@ __device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, i
 // and rinfo[r] (runs | 0x100: first run at column 0 | 0x200: last run ends
 // at column 63).
 template <int TH, int RPW, bool CONN8>
-__device__ __forceinline__ void sweep_band_eq(uint32_t *par, uint8_t *col, uint64_t *msk,
+__device__ __forceinline__ void sweep_band_eq(uint32_t *par, uint16_t *cr, uint64_t *msk,
                                               uint16_t *rinfo, const uint8_t *pix, int wave,
                                               int lane, int wlim, int hlim) {
     constexpr int SPR = slots_per_row<true>();
@@ -523,7 +550,7 @@ __device__ __forceinline__ void sweep_band_eq(uint32_t *par, uint8_t *col, uint6
         uint32_t *pn = &par[node];
         if (isS) {
             lds_st(pn, node);
-            col[node] = (uint8_t)lane;
+            cr[node] = (uint16_t)(lane | (r << 8));
         }
         if (lane == 0) {
             msk[r] = S;

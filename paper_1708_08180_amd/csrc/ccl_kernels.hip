@@ -30,10 +30,11 @@ template <int TH, bool EQ>
 struct K1Lds {
     static constexpr int SPR = slots_per_row<EQ>();
     uint32_t par[TH * SPR];  // run-indexed parents
-    uint8_t col[TH * SPR];   // first column of every run
+    uint16_t cr[TH * SPR];   // every run's first column | row << 8
     uint64_t msk[TH];        // per row: foreground mask (binary) / run starts (equal-value)
     uint64_t flg[TH];        // per row: local roots of edge-touching components
     uint16_t rinfo[TH];      // runs | 0x100: first run at column 0 | 0x200: last ends at 63
+    uint16_t rbase[TH];      // first node of every row (binary: dense numbering)
     alignas(16) uint8_t pix[EQ ? TH * kTileW : 16];  // the tile's bytes (equal-value only)
 };
 
@@ -50,10 +51,11 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
     constexpr int NODES = TH * SPR;             // run-indexed nodes per tile
     constexpr int NPT = (NODES + NT - 1) / NT;  // nodes per thread
     uint32_t *par = sh.par;
-    uint8_t *col = sh.col;
+    uint16_t *cr = sh.cr;
     uint64_t *msk = sh.msk;
     uint64_t *flg = sh.flg;
     uint16_t *rinfo = sh.rinfo;
+    uint16_t *rbase = sh.rbase;
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t TX = (uint32_t)v.tilesX;
     const int tx = (int)(t % TX), ty = (int)(t / TX);
@@ -74,23 +76,32 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
     }
     if (tid < TH) flg[tid] = 0ull;
     __syncthreads();
+    // first node of every row, one row per lane: binary labeling numbers the
+    // runs densely (an exclusive scan of the rows' run counts, so the finish
+    // pass visits only real runs); equal-value labeling keeps 64 per row
+    uint32_t rbv, nodes;
     if (EQ) {
-        sweep_band_eq<TH, RPW, CONN8>(par, col, msk, rinfo, sh.pix, wave, lane, wlim, hlim);
+        rbv = (uint32_t)(lane * SPR);
+        nodes = (uint32_t)NODES;
     } else {
-        // per-row run counts and edge bits, one row per thread (read after
-        // the barriers that follow the sweep)
+        const uint64_t dj = lane < TH ? msk[lane] : 0ull;
+        rbv = wave_exclusive_scan((uint32_t)__popcll(run_starts(dj)), &nodes);
         if (tid < TH) {
-            const uint64_t d = msk[tid];
-            rinfo[tid] = (uint16_t)(__popcll(run_starts(d)) | ((d & 1ull) ? 0x100 : 0) |
-                                    ((d >> 63) ? 0x200 : 0));
+            rinfo[tid] = (uint16_t)(__popcll(run_starts(dj)) | ((dj & 1ull) ? 0x100 : 0) |
+                                    ((dj >> 63) ? 0x200 : 0));
+            rbase[tid] = (uint16_t)rbv;
         }
-        sweep_band<TH, RPW, CONN8>(par, col, msk, wave, lane);
+    }
+    if (EQ) {
+        sweep_band_eq<TH, RPW, CONN8>(par, cr, msk, rinfo, sh.pix, wave, lane, wlim, hlim);
+    } else {
+        sweep_band<TH, RPW, CONN8>(par, cr, msk, wave, lane, rbv);
     }
     if (NW > 1) {
         __syncthreads();
         if (wave > 0) {
             if (EQ) merge_seam_eq<CONN8>(par, msk, sh.pix, wave * RPW, lane, wlim, hlim);
-            else merge_seam<CONN8>(par, msk, wave * RPW);
+            else merge_seam<CONN8>(par, msk, wave * RPW, rbv);
         }
     }
     __syncthreads();
@@ -103,24 +114,34 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
         const int n = tid + i * NT;
-        if (n >= NODES) break;
-        const int r = n / SPR, k = n % SPR;
+        if (n >= (int)nodes) break;
+        int r, k;
+        if (EQ) {
+            r = n / SPR;
+            k = n % SPR;
+        } else {
+            r = cr[n] >> 8;
+            k = n - (int)rbase[r];
+        }
         const uint32_t info = rinfo[r];
         const int runs = (int)(info & 0x7Fu);
         if (k >= runs) continue;
         const uint32_t root = lds_root(par, (uint32_t)n);
         if (root != (uint32_t)n) lds_st(&par[n], root);
-        const uint32_t rc = col[root];
-        sl[n] = (uint16_t)((root / SPR) * kTileW + rc);
+        const uint32_t c = cr[root];
+        const uint32_t rc = c & 0xFFu;
+        sl[n] = (uint16_t)((c >> 8) * kTileW + rc);
         const bool edge = (r == 0 && hasUp) || (r == TH - 1 && hasDown) ||
                           (k == 0 && (info & 0x100u) && hasLeft) ||
                           (k == runs - 1 && (info & 0x200u) && hasRight);
-        if (edge) atomicOr((unsigned long long *)&flg[root / SPR], 1ull << rc);
+        if (edge) atomicOr((unsigned long long *)&flg[c >> 8], 1ull << rc);
     }
     __syncthreads();
     if (tid < TH) {
-        v.rowmask[(size_t)t * 2 * TH + tid] = msk[tid];
-        v.rowmask[(size_t)t * 2 * TH + TH + tid] = flg[tid];
+        uint64_t *rw = v.rowmask + (size_t)t * rowmask_words(TH);
+        rw[tid] = msk[tid];
+        rw[TH + tid] = flg[tid];
+        if (!EQ) ((uint16_t *)(rw + 2 * TH))[tid] = rbase[tid];
     }
     // edge masks and edge-cell roots for the boundary analysis; every such
     // root is seeded in the forest (lanes of one component store the same
@@ -136,20 +157,22 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
         const uint64_t sBot = EQ ? uniform64(msk[TH - 1]) : run_starts(mBot);
         // global index of the root pixel of run node n
         auto root_g = [&](uint32_t n) {
-            const uint32_t root = lds_ld(&par[n]);
-            return global_index(v, tx, ty, TH, (root / SPR) * kTileW + col[root]);
+            const uint32_t c = cr[lds_ld(&par[n])];
+            return global_index(v, tx, ty, TH, (c >> 8) * kTileW + (c & 0xFFu));
         };
         auto put = [&](uint32_t *dst, uint32_t g) {
             *dst = g;
             v.labels[g] = g + 1u;
         };
+        // first node of the bottom row, read while every lane is active (a
+        // lane that is off inside the branch below may not hold it)
+        const uint32_t rbBot = (uint32_t)__builtin_amdgcn_readlane((int)rbv, TH - 1);
         if (hasUp && lane_in(mTop)) {
             const uint32_t n = bits_below(sTop) - (lane_in(sTop) ? 0u : 1u);
             put(&rt[roots_top(TH) + lane], root_g(n));
         }
         if (hasDown && lane_in(mBot)) {
-            const uint32_t n = (uint32_t)((TH - 1) * SPR) + bits_below(sBot) -
-                               (lane_in(sBot) ? 0u : 1u);
+            const uint32_t n = rbBot + bits_below(sBot) - (lane_in(sBot) ? 0u : 1u);
             put(&rt[roots_bottom(TH) + lane], root_g(n));
         }
         // per row (lane = row): cells in the left / right column, last run
@@ -159,9 +182,8 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
         const bool rb = EQ ? (rowIn && wlim == 64) : (mr >> 63) != 0;
         const int lastRun = __popcll(EQ ? mr : run_starts(mr)) - 1;
         const uint64_t mLeft = __ballot(lb), mRight = __ballot(rb);
-        if (hasLeft && lb) put(&rt[roots_left(TH) + lane], root_g((uint32_t)(lane * SPR)));
-        if (hasRight && rb)
-            put(&rt[roots_right(TH) + lane], root_g((uint32_t)(lane * SPR + lastRun)));
+        if (hasLeft && lb) put(&rt[roots_left(TH) + lane], root_g(rbv));
+        if (hasRight && rb) put(&rt[roots_right(TH) + lane], root_g(rbv + (uint32_t)lastRun));
         if (lane == 0) {
             mk[kMaskTop] = mTop;
             mk[kMaskBottom] = mBot;
@@ -318,14 +340,24 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t W = (uint32_t)v.W;
-    const uint64_t *rm = v.rowmask + (size_t)t * 2 * TH + wave * RPW;
-    const uint16_t *sl = v.slots + (size_t)t * TH * SPR + wave * RPW * SPR;
+    const uint64_t *rm = v.rowmask + (size_t)t * rowmask_words(TH) + wave * RPW;
+    const uint16_t *sl = v.slots + (size_t)t * TH * SPR;
     // global index of the tile's pixel (0, 0); every label fits in 32 bits
     const uint32_t origin = ty * (uint32_t)TH * W + tx * (uint32_t)kTileW;
     // equal-value: every in-image pixel takes part (rows hold run starts)
     const int wlim = min(kTileW, v.W - (int)tx * kTileW);
     const uint64_t cols = wlim == 64 ? ~0ull : ((1ull << wlim) - 1ull);
     const int rows_in = v.H - (int)ty * TH - wave * RPW;
+    // first record of this wave's rows (lane k: row wave*RPW + k): binary
+    // records are numbered densely by the local merge, which stored every
+    // row's first record; equal-value records have 64 slots per row
+    uint32_t rbv;
+    if (EQ) {
+        rbv = (uint32_t)((wave * RPW + lane) * SPR);
+    } else {
+        const uint16_t *rbg = (const uint16_t *)(v.rowmask + (size_t)t * rowmask_words(TH) + 2 * TH);
+        rbv = lane < RPW ? (uint32_t)rbg[wave * RPW + lane] : 0u;
+    }
     uint64_t m[RPW], f[RPW];
     uint32_t rec[RPW];
 #pragma unroll
@@ -341,7 +373,8 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *
         const uint64_t S = EQ ? m[k] : run_starts(m[k]);
         const uint32_t below = bits_below(S) + (lane_in(S) ? 1u : 0u);
         const uint32_t rank = below ? below - 1u : 0u;
-        const uint32_t r = sl[k * SPR + rank];
+        const uint32_t rb = (uint32_t)__builtin_amdgcn_readlane((int)rbv, k);
+        const uint32_t r = sl[rb + rank];
         rec[k] = lane_in(d) ? r : kNone;
     }
 #pragma unroll
@@ -412,7 +445,7 @@ __device__ __forceinline__ ImgView batch_view(const BatchImage &b, const BatchWs
     v.labels = b.labels;
     v.masks = w.masks + (size_t)b.tile_base * 4;
     v.roots = w.roots + (size_t)b.tile_base * roots_per_tile(TH);
-    v.rowmask = w.rowmask + (size_t)b.tile_base * 2 * TH;
+    v.rowmask = w.rowmask + (size_t)b.tile_base * rowmask_words(TH);
     v.slots = w.slots + (size_t)b.tile_base * TH * kSlotsPerRow;
     v.pitch = b.pitch;
     v.H = b.H;

@@ -62,7 +62,7 @@ template <int CONN>
 __global__ void __launch_bounds__(256) k1_local_merge3d(Vol v) {
     constexpr bool CONN8 = CONN != 6;  // neighbours inside a slice
     __shared__ uint32_t par[kRows * kSlotsPerRow];
-    __shared__ uint8_t col[kRows * kSlotsPerRow];
+    __shared__ uint16_t cr[kRows * kSlotsPerRow];
     __shared__ uint64_t msk[kRows];
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int tx, ty, tz;
@@ -75,20 +75,21 @@ __global__ void __launch_bounds__(256) k1_local_merge3d(Vol v) {
     }
     __syncthreads();
     // wavefront w sweeps slice w (rows w*16 .. w*16+15)
-    sweep_band<kRows, kTY, CONN8>(par, col, msk, wave, lane);
+    sweep_band<kRows, kTY, CONN8>(par, cr, msk, wave, lane, (uint32_t)(lane * kSlotsPerRow));
     __syncthreads();
     if (wave > 0) {
         // rows of slice w against the rows of slice w-1 they touch
         for (int yi = 0; yi < kTY; ++yi) {
             const int r = wave * kTY + yi, ru = (wave - 1) * kTY + yi;
+            const uint32_t b = (uint32_t)(r * kSlotsPerRow), bu = (uint32_t)(ru * kSlotsPerRow);
             if (CONN == 6) {
-                merge_rows<false>(par, msk, r, ru);
+                merge_rows<false>(par, msk, r, ru, b, bu);
             } else {
-                merge_rows<true>(par, msk, r, ru);
+                merge_rows<true>(par, msk, r, ru, b, bu);
                 // the rows above and below in the previous slice: straight
                 // (18: an edge neighbour) or with diagonals (26: corners too)
-                if (yi > 0) merge_rows<CONN == 26>(par, msk, r, ru - 1);
-                if (yi + 1 < kTY) merge_rows<CONN == 26>(par, msk, r, ru + 1);
+                if (yi > 0) merge_rows<CONN == 26>(par, msk, r, ru - 1, b, bu - kSlotsPerRow);
+                if (yi + 1 < kTY) merge_rows<CONN == 26>(par, msk, r, ru + 1, b, bu + kSlotsPerRow);
             }
         }
     }
@@ -113,10 +114,10 @@ __global__ void __launch_bounds__(256) k1_local_merge3d(Vol v) {
         if (lane_in(d)) {
             const uint64_t S = run_starts(d);
             const uint32_t node = (uint32_t)(r * kSlotsPerRow) + bits_below(S) - (lane_in(S) ? 0u : 1u);
-            const uint32_t root = lds_ld(&par[node]);
-            const uint32_t rr = root / kSlotsPerRow;
+            const uint32_t c = cr[lds_ld(&par[node])];
+            const uint32_t rr = c >> 8;
             const uint64_t g = ((uint64_t)(z0 + rr / kTY) * v.H + (uint64_t)(y0 + rr % kTY)) * v.W +
-                               (uint64_t)(x0 + col[root]);
+                               (uint64_t)(x0 + (c & 0xFFu));
             out = (uint32_t)g + 1u;
         }
         v.labels[((uint64_t)z * v.H + y) * v.W + x] = out;
