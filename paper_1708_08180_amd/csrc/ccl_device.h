@@ -529,7 +529,7 @@ __device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, i
 // and rinfo[r] (runs | 0x100: first run at column 0 | 0x200: last run ends
 // at column 63).
 template <int TH, int RPW, bool CONN8>
-__device__ __forceinline__ void sweep_band_eq(uint32_t *par, uint16_t *cr, uint64_t *msk,
+__device__ __forceinline__ void sweep_band_eq(uint32_t *par, uint8_t *col, uint64_t *msk,
                                               uint16_t *rinfo, const uint8_t *pix, int wave,
                                               int lane, int wlim, int hlim) {
     constexpr int SPR = slots_per_row<true>();
@@ -550,7 +550,7 @@ __device__ __forceinline__ void sweep_band_eq(uint32_t *par, uint16_t *cr, uint6
         uint32_t *pn = &par[node];
         if (isS) {
             lds_st(pn, node);
-            cr[node] = (uint16_t)(lane | (r << 8));
+            col[node] = (uint8_t)lane;
         }
         if (lane == 0) {
             msk[r] = S;

@@ -19,6 +19,8 @@
 // boundary analysis) and the batch kernels (the same bodies over one global
 // numbering of the tiles of all images).
 
+#include <type_traits>
+
 #include "ccl_device.h"
 #include "ccl_internal.h"
 
@@ -29,8 +31,11 @@ namespace ccl {
 template <int TH, bool EQ>
 struct K1Lds {
     static constexpr int SPR = slots_per_row<EQ>();
+    // every run's first column | row << 8 (equal-value: the column only; the
+    // row of node n is n / 64 there)
+    using CR = typename std::conditional<EQ, uint8_t, uint16_t>::type;
     uint32_t par[TH * SPR];  // run-indexed parents
-    uint16_t cr[TH * SPR];   // every run's first column | row << 8
+    CR cr[TH * SPR];
     uint64_t msk[TH];        // per row: foreground mask (binary) / run starts (equal-value)
     uint64_t flg[TH];        // per row: local roots of edge-touching components
     uint16_t rinfo[TH];      // runs | 0x100: first run at column 0 | 0x200: last ends at 63
@@ -51,12 +56,16 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
     constexpr int NODES = TH * SPR;             // run-indexed nodes per tile
     constexpr int NPT = (NODES + NT - 1) / NT;  // nodes per thread
     uint32_t *par = sh.par;
-    uint16_t *cr = sh.cr;
+    typename K1Lds<TH, EQ>::CR *cr = sh.cr;
+    // tile row and first column of run node n
+    auto run_row = [&](uint32_t n) { return EQ ? n / (uint32_t)SPR : (uint32_t)cr[n] >> 8; };
+    auto run_col = [&](uint32_t n) { return (uint32_t)cr[n] & 0xFFu; };
     uint64_t *msk = sh.msk;
     uint64_t *flg = sh.flg;
     uint16_t *rinfo = sh.rinfo;
     uint16_t *rbase = sh.rbase;
-    const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = (int)threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     const uint32_t TX = (uint32_t)v.tilesX;
     const int tx = (int)(t % TX), ty = (int)(t / TX);
     const bool hasUp = ty > 0, hasDown = ty + 1 < v.tilesY;
@@ -92,7 +101,7 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
             rbase[tid] = (uint16_t)rbv;
         }
     }
-    if (EQ) {
+    if constexpr (EQ) {
         sweep_band_eq<TH, RPW, CONN8>(par, cr, msk, rinfo, sh.pix, wave, lane, wlim, hlim);
     } else {
         sweep_band<TH, RPW, CONN8>(par, cr, msk, wave, lane, rbv);
@@ -120,7 +129,7 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
             r = n / SPR;
             k = n % SPR;
         } else {
-            r = cr[n] >> 8;
+            r = (int)run_row((uint32_t)n);
             k = n - (int)rbase[r];
         }
         const uint32_t info = rinfo[r];
@@ -128,13 +137,12 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
         if (k >= runs) continue;
         const uint32_t root = lds_root(par, (uint32_t)n);
         if (root != (uint32_t)n) lds_st(&par[n], root);
-        const uint32_t c = cr[root];
-        const uint32_t rc = c & 0xFFu;
-        sl[n] = (uint16_t)((c >> 8) * kTileW + rc);
+        const uint32_t rr = run_row(root), rc = run_col(root);
+        sl[n] = (uint16_t)(rr * kTileW + rc);
         const bool edge = (r == 0 && hasUp) || (r == TH - 1 && hasDown) ||
                           (k == 0 && (info & 0x100u) && hasLeft) ||
                           (k == runs - 1 && (info & 0x200u) && hasRight);
-        if (edge) atomicOr((unsigned long long *)&flg[c >> 8], 1ull << rc);
+        if (edge) atomicOr((unsigned long long *)&flg[rr], 1ull << rc);
     }
     __syncthreads();
     if (tid < TH) {
@@ -157,8 +165,8 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
         const uint64_t sBot = EQ ? uniform64(msk[TH - 1]) : run_starts(mBot);
         // global index of the root pixel of run node n
         auto root_g = [&](uint32_t n) {
-            const uint32_t c = cr[lds_ld(&par[n])];
-            return global_index(v, tx, ty, TH, (c >> 8) * kTileW + (c & 0xFFu));
+            const uint32_t root = lds_ld(&par[n]);
+            return global_index(v, tx, ty, TH, run_row(root) * kTileW + run_col(root));
         };
         auto put = [&](uint32_t *dst, uint32_t g) {
             *dst = g;
