@@ -184,15 +184,17 @@ __device__ __forceinline__ uint32_t lds_root(const uint32_t *par, uint32_t x) {
     }
 }
 
-// Link the two trees of a and b, the larger root under the smaller
-// (Sec. II-A-3).  When the atomicMin finds that b stopped being a root in
-// the meantime, the value it returns is b's new parent and the merge is
-// retried from there, so no concurrent link is ever lost.
+// Join the trees of a and b (Sec. II-A-3), the larger index under the
+// smaller, without a find first: the atomicMin lowers the larger node's
+// parent to the smaller node and returns the parent it had.  If that was
+// the node itself, a root was linked and the merge is done; otherwise the
+// node is now the smaller one's child, its old parent still has to be
+// joined to it, and the step repeats on that pair.  The larger index of
+// the pair drops every step, so the walk ends; every parent only ever
+// moves to a smaller node connected to it, so no concurrent link is lost.
+// Callers mostly pass two roots, which makes this a single atomic.
 __device__ __forceinline__ void lds_union(uint32_t *par, uint32_t a, uint32_t b) {
-    while (true) {
-        a = lds_root(par, a);
-        b = lds_root(par, b);
-        if (a == b) return;
+    while (a != b) {
         if (a > b) { const uint32_t t = a; a = b; b = t; }
         const uint32_t old = atomicMin(&par[b], a);
         if (old >= b) return;

@@ -38,7 +38,7 @@ struct K1Lds {
     CR cr[TH * SPR];
     uint64_t msk[TH];        // per row: foreground mask (binary) / run starts (equal-value)
     uint64_t flg[TH];        // per row: local roots of edge-touching components
-    uint16_t rinfo[TH];      // runs | 0x100: first run at column 0 | 0x200: last ends at 63
+    uint16_t rinfo[TH];      // equal-value: runs | 0x100: first run at column 0 | 0x200: last ends at 63
     uint16_t rbase[TH];      // first node of every row (binary: dense numbering)
     alignas(16) uint8_t pix[EQ ? TH * kTileW : 16];  // the tile's bytes (equal-value only)
 };
@@ -95,11 +95,7 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
     } else {
         const uint64_t dj = lane < TH ? msk[lane] : 0ull;
         rbv = wave_exclusive_scan((uint32_t)__popcll(run_starts(dj)), &nodes);
-        if (tid < TH) {
-            rinfo[tid] = (uint16_t)(__popcll(run_starts(dj)) | ((dj & 1ull) ? 0x100 : 0) |
-                                    ((dj >> 63) ? 0x200 : 0));
-            rbase[tid] = (uint16_t)rbv;
-        }
+        if (tid < TH) rbase[tid] = (uint16_t)rbv;
     }
     if constexpr (EQ) {
         sweep_band_eq<TH, RPW, CONN8>(par, cr, msk, rinfo, sh.pix, wave, lane, wlim, hlim);
@@ -117,38 +113,22 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
 
     // node-parallel finish: every node finds its root (read-only walk) and
     // its owner alone stores it, so par[n] is the root afterwards; the run's
-    // record (the root's tile-local pixel) goes out, and edge runs mark
-    // their root pixel in the edge-root masks.
+    // record (the root's tile-local pixel) goes out
     uint16_t *sl = v.slots + (size_t)t * TH * SPR;
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
         const int n = tid + i * NT;
         if (n >= (int)nodes) break;
-        int r, k;
-        if (EQ) {
-            r = n / SPR;
-            k = n % SPR;
-        } else {
-            r = (int)run_row((uint32_t)n);
-            k = n - (int)rbase[r];
-        }
-        const uint32_t info = rinfo[r];
-        const int runs = (int)(info & 0x7Fu);
-        if (k >= runs) continue;
+        // equal-value numbering leaves unused slots at the end of each row
+        if (EQ && n % SPR >= (int)(rinfo[n / SPR] & 0x7Fu)) continue;
         const uint32_t root = lds_root(par, (uint32_t)n);
         if (root != (uint32_t)n) lds_st(&par[n], root);
-        const uint32_t rr = run_row(root), rc = run_col(root);
-        sl[n] = (uint16_t)(rr * kTileW + rc);
-        const bool edge = (r == 0 && hasUp) || (r == TH - 1 && hasDown) ||
-                          (k == 0 && (info & 0x100u) && hasLeft) ||
-                          (k == runs - 1 && (info & 0x200u) && hasRight);
-        if (edge) atomicOr((unsigned long long *)&flg[rr], 1ull << rc);
+        sl[n] = (uint16_t)(run_row(root) * kTileW + run_col(root));
     }
     __syncthreads();
     if (tid < TH) {
         uint64_t *rw = v.rowmask + (size_t)t * rowmask_words(TH);
         rw[tid] = msk[tid];
-        rw[TH + tid] = flg[tid];
         if (!EQ) ((uint16_t *)(rw + 2 * TH))[tid] = rbase[tid];
     }
     // edge masks and edge-cell roots for the boundary analysis; every such
@@ -163,10 +143,13 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
         const uint64_t mBot = EQ ? (TH - 1 < hlim ? cols : 0ull) : uniform64(msk[TH - 1]);
         const uint64_t sTop = EQ ? uniform64(msk[0]) : run_starts(mTop);
         const uint64_t sBot = EQ ? uniform64(msk[TH - 1]) : run_starts(mBot);
-        // global index of the root pixel of run node n
+        // global index of the root pixel of run node n; the root is marked
+        // in the edge-root masks (its component touches a shared edge)
         auto root_g = [&](uint32_t n) {
             const uint32_t root = lds_ld(&par[n]);
-            return global_index(v, tx, ty, TH, run_row(root) * kTileW + run_col(root));
+            const uint32_t rr = run_row(root), rc = run_col(root);
+            atomicOr((unsigned long long *)&flg[rr], 1ull << rc);
+            return global_index(v, tx, ty, TH, rr * kTileW + rc);
         };
         auto put = [&](uint32_t *dst, uint32_t g) {
             *dst = g;
@@ -198,6 +181,11 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
             mk[kMaskLeft] = mLeft;
             mk[kMaskRight] = mRight;
         }
+        // only this wavefront marks edge roots: once its own LDS operations
+        // have completed, the masks are whole
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (lane < TH) v.rowmask[(size_t)t * rowmask_words(TH) + TH + lane] = flg[lane];
     }
     __syncthreads();  // LDS may be reused for another tile
 }
