@@ -291,9 +291,16 @@ __device__ __forceinline__ void union_requests(uint32_t *L, uint32_t n, const ui
     if (mb != kNone) g_union(L, n, ma, mb);
 }
 
-// Find for the link phase.  No link is made any more, so every root is
-// final and every path node may be overwritten with the root (full path
-// compression with plain stores: all writers store the same value).
+// Root of x once no link is made any more (link phase).
+__device__ __forceinline__ uint32_t g_root(const uint32_t *L, uint32_t x) {
+    uint32_t v = L[x] - 1u;
+    while (v < x) { x = v; v = L[x] - 1u; }
+    return x;
+}
+
+// The same with full path compression: every root is final, so every path
+// node may be overwritten with the root (plain stores: all writers store
+// the same value).
 __device__ __forceinline__ uint32_t g_find_final(uint32_t *L, uint32_t x) {
     uint32_t r = x;
     uint32_t v = L[r] - 1u;
@@ -365,6 +372,10 @@ __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_in
 __device__ __forceinline__ uint32_t bits_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
+// acc + the set bits of m below this lane
+__device__ __forceinline__ uint32_t bits_below_plus(uint64_t m, uint32_t acc) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, acc));
+}
 
 // Value of lane-1 / lane+1 (whole-wave DPP shifts; lane 0 / 63 get `edge`).
 __device__ __forceinline__ uint32_t from_left(uint32_t v, uint32_t edge) {
@@ -375,6 +386,8 @@ __device__ __forceinline__ uint32_t from_right(uint32_t v, uint32_t edge) {
 }
 
 __device__ __forceinline__ uint64_t run_starts(uint64_t d) { return d & ~(d << 1); }
+// last cell of every run
+__device__ __forceinline__ uint64_t run_ends(uint64_t d) { return d & ~(d >> 1); }
 
 // Exclusive prefix sum over the 64 lanes of a wavefront; *total gets the
 // sum of all lanes.
@@ -431,14 +444,18 @@ __device__ __forceinline__ PairMasks pair_masks(uint64_t d, uint64_t u, uint64_t
 // `ra` carries, per lane, the root node of the pixel above (kNone for
 // background), so the roots a run touches come from neighbouring lanes'
 // registers.  A run's parent becomes the smallest of those roots (one LDS
-// atomicMin per lane on its node); every other root it touches is joined
-// to that one by a real union, which is rare.  Only after a row that had one
-// are the row's roots re-resolved, so `ra` always holds true roots.
+// atomicMin per lane on its node).  Every other root it touches is then
+// linked under that one; they were roots when the row began, so one
+// atomicMin per link normally does it, and only a link that finds its root
+// already linked elsewhere in this row continues as a general union.  After
+// a row with links the row's roots are re-resolved, so `ra` always holds
+// true roots.
 //
 // Node numbering: the first node of tile row j is lane j's value of `rbv`
 // (a row's nodes are consecutive and rows follow each other, so nodes stay
 // in raster order of run starts): either dense, an exclusive scan of the
-// rows' run counts, or sparse, j * 32.  cr[node] = first column | row << 8.
+// rows' run counts, or sparse, j * 32.  A foreground cell's run follows the
+// runs that end before it.  cr[node] = first column | row << 8.
 template <int TH, int RPW, bool CONN8>
 __device__ __forceinline__ void sweep_band(uint32_t *par, uint16_t *cr, const uint64_t *msk,
                                            int wave, int lane, uint32_t rbv) {
@@ -454,7 +471,7 @@ __device__ __forceinline__ void sweep_band(uint32_t *par, uint16_t *cr, const ui
         const uint64_t S = run_starts(d);
         const bool fg = lane_in(d), isS = lane_in(S);
         const uint32_t rb = (uint32_t)__builtin_amdgcn_readlane((int)rbv, r);
-        const uint32_t node = rb + bits_below(S) - (isS ? 0u : 1u);
+        const uint32_t node = bits_below_plus(run_ends(d), rb);
         uint32_t *pn = &par[node];
         if (isS) {
             lds_st(pn, node);
@@ -464,16 +481,23 @@ __device__ __forceinline__ void sweep_band(uint32_t *par, uint16_t *cr, const ui
         if (k > 0) {
             const PairMasks p = pair_masks<CONN8>(d, u);
             const uint32_t rL = from_left(ra, kNone), rR = from_right(ra, kNone);
-            const uint32_t t0 = lane_in(p.pl) ? rL : (lane_in(p.pm) ? ra : kNone);
+            // PL and PM are disjoint
+            const uint32_t t0 = lane_in(p.pm) ? ra : (lane_in(p.pl) ? rL : kNone);
             const uint32_t t1 = lane_in(p.pr) ? rR : kNone;
             const uint32_t tm = t0 < t1 ? t0 : t1;
             if (tm != kNone) atomicMin(pn, tm);
-            if (fg) md = lds_ld(pn);
+            if (fg) md = lds_ld(pn);  // the smallest root the run touches
             const bool n0 = t0 != kNone && t0 != md;
             const bool n1 = t1 != kNone && t1 != md;
             if (__ballot(n0 || n1)) {
-                if (n0) lds_union(par, t0, md);
-                if (n1) lds_union(par, t1, md);
+                uint32_t o0 = 0, o1 = 0;
+                if (n0) o0 = atomicMin(&par[t0], md);
+                if (n1) o1 = atomicMin(&par[t1], md);
+                const bool r0 = n0 && o0 < t0, r1 = n1 && o1 < t1;
+                if (__ballot(r0 || r1)) {
+                    if (r0) lds_union(par, md, o0);
+                    if (r1) lds_union(par, md, o1);
+                }
                 if (fg) md = lds_root(par, md);
                 if (isS) lds_st(pn, md);
             }

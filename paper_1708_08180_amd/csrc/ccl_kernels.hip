@@ -320,15 +320,24 @@ __device__ __forceinline__ void k2_tile_eq(const ImgView &v, uint32_t t) {
 
 // Link body for tile t (Sec. II-C): the local merge left the tile's row
 // masks, the masks of its local roots whose components touch a shared tile
-// edge, and per run its tile-local root pixel.  Every
-// local root pixel first puts its final label - 1 into fin[]: flagged roots
-// are resolved once in the global forest (and, being rewritten with their
-// final value, compressed for the tiles that still walk through them),
-// unflagged roots are already final.  Then every pixel reads its root's
-// entry; output rows are full 256-byte lines.  Ends after a workgroup
-// barrier.
+// edge ("flagged" roots), and per run its tile-local root pixel.  Every
+// local root pixel first puts its final label - 1 into fin[]: unflagged
+// roots are already final; flagged roots are resolved in the global forest
+// (where a tile's stores of final labels compress the paths of the tiles
+// that still walk through its pixels).  A wavefront lists the flagged roots of
+// its rows in LDS and resolves them all at once, one per lane, so their
+// walks overlap instead of following each other row by row.  Then every
+// pixel reads its root's entry; output rows are full 256-byte lines.  Ends
+// after a workgroup barrier.
+//
+// A flagged root is the root of some edge cell, so a tile has at most
+// 2 * 64 + 2 * TH <= kFlagCap of them; `flist` holds kFlagCap entries per
+// wavefront.
+constexpr int kFlagCap = 256;
+
 template <int TH, int NW, bool EQ>
-__device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *fin) {
+__device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *fin, uint16_t *flist) {
+    static_assert(2 * kTileW + 2 * TH <= kFlagCap, "flagged-root list too small");
     constexpr int SPR = slots_per_row<EQ>();
     constexpr int RPW = TH / NW;
     const uint32_t TX = (uint32_t)v.tilesX;
@@ -373,13 +382,29 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *
         const uint32_t r = sl[rb + rank];
         rec[k] = lane_in(d) ? r : kNone;
     }
+    // this wave's flagged roots, listed in row order
+    uint16_t *fl = flist + wave * kFlagCap;
+    uint32_t nf = 0;
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+        const uint32_t pos = nf + bits_below(f[k]);
+        if (lane_in(f[k]) && pos < (uint32_t)kFlagCap)
+            fl[pos] = (uint16_t)((wave * RPW + k) * kTileW + lane);
+        nf += (uint32_t)__popcll(f[k]);
+    }
+    nf = min(nf, (uint32_t)kFlagCap);
+    // unflagged local roots are final
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
         const uint32_t l = (uint32_t)((wave * RPW + k) * kTileW + lane);
-        if (rec[k] == l) {
-            const uint32_t g = origin + (l >> 6) * W + (l & 63u);
-            fin[l] = lane_in(f[k]) ? g_find_final(v.labels, g) : g;
-        }
+        if (rec[k] == l && !lane_in(f[k])) fin[l] = origin + (l >> 6) * W + (l & 63u);
+    }
+    // the list is read back by other lanes of this wavefront
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t i = (uint32_t)lane; i < nf; i += 64u) {
+        const uint32_t l = fl[i];
+        fin[l] = g_root(v.labels, origin + (l >> 6) * W + (l & 63u));
     }
     __syncthreads();
     const uint32_t x = tx * (uint32_t)kTileW + (uint32_t)lane;
@@ -413,7 +438,8 @@ __global__ void __launch_bounds__(256) k2_boundary(ImgView v, uint32_t tiles) {
 template <int TH, int NW, bool EQ>
 __global__ void __launch_bounds__(NW * 64) k3_link(ImgView v) {
     __shared__ uint32_t fin[TH * kTileW];
-    k3_tile<TH, NW, EQ>(v, xcd_remap(blockIdx.x, gridDim.x), fin);
+    __shared__ uint16_t flist[NW * kFlagCap];
+    k3_tile<TH, NW, EQ>(v, xcd_remap(blockIdx.x, gridDim.x), fin, flist);
 }
 
 // ------------------------------------------------------------ batch kernels
@@ -479,10 +505,11 @@ __global__ void __launch_bounds__(256) k2_batch(BatchArgs a) {
 template <int TH, int NW>
 __global__ void __launch_bounds__(NW * 64) k3_batch(BatchArgs a) {
     __shared__ uint32_t fin[TH * kTileW];
+    __shared__ uint16_t flist[NW * kFlagCap];
     const uint32_t g = xcd_remap(blockIdx.x, gridDim.x);
     if (g >= a.tiles) return;  // workgroup-uniform
     const BatchImage &d = a.descs[a.w.tile_img[g]];
-    k3_tile<TH, NW, false>(batch_view<TH>(d, a.w), g - d.tile_base, fin);
+    k3_tile<TH, NW, false>(batch_view<TH>(d, a.w), g - d.tile_base, fin, flist);
 }
 
 // ---------------------------------------------------------------- launchers
