@@ -184,16 +184,32 @@ __device__ __forceinline__ uint32_t lds_root(const uint32_t *par, uint32_t x) {
     }
 }
 
-// Join the trees of a and b (Sec. II-A-3), the larger index under the
-// smaller, without a find first: the atomicMin lowers the larger node's
-// parent to the smaller node and returns the parent it had.  If that was
-// the node itself, a root was linked and the merge is done; otherwise the
-// node is now the smaller one's child, its old parent still has to be
-// joined to it, and the step repeats on that pair.  The larger index of
-// the pair drops every step, so the walk ends; every parent only ever
-// moves to a smaller node connected to it, so no concurrent link is lost.
-// Callers mostly pass two roots, which makes this a single atomic.
+// Join the trees of a and b (Sec. II-A-3): find both roots, link the
+// larger under the smaller.  When the atomicMin finds that b stopped being
+// a root in the meantime, the value it returns is b's new parent and the
+// merge is retried from there, so no concurrent link is ever lost.  For
+// arbitrary nodes (band seams, slice merges).
 __device__ __forceinline__ void lds_union(uint32_t *par, uint32_t a, uint32_t b) {
+    while (true) {
+        a = lds_root(par, a);
+        b = lds_root(par, b);
+        if (a == b) return;
+        if (a > b) { const uint32_t t = a; a = b; b = t; }
+        const uint32_t old = atomicMin(&par[b], a);
+        if (old >= b) return;
+        b = old;
+    }
+}
+
+// The same join without a find first, for two nodes that are normally
+// roots: the atomicMin lowers the larger node's parent to the smaller node
+// and returns the parent it had.  If that was the node itself, a root was
+// linked and the merge is done; otherwise the node is now the smaller
+// one's child, its old parent still has to be joined to it, and the step
+// repeats on that pair.  The larger index of the pair drops every step, so
+// the walk ends; every parent only ever moves to a smaller node connected
+// to it, so no concurrent link is lost.
+__device__ __forceinline__ void lds_link(uint32_t *par, uint32_t a, uint32_t b) {
     while (a != b) {
         if (a > b) { const uint32_t t = a; a = b; b = t; }
         const uint32_t old = atomicMin(&par[b], a);
@@ -493,10 +509,10 @@ __device__ __forceinline__ void sweep_band(uint32_t *par, uint16_t *cr, const ui
                 uint32_t o0 = 0, o1 = 0;
                 if (n0) o0 = atomicMin(&par[t0], md);
                 if (n1) o1 = atomicMin(&par[t1], md);
-                const bool r0 = n0 && o0 < t0, r1 = n1 && o1 < t1;
+                const bool r0 = n0 && o0 < t0 && o0 != md, r1 = n1 && o1 < t1 && o1 != md;
                 if (__ballot(r0 || r1)) {
-                    if (r0) lds_union(par, md, o0);
-                    if (r1) lds_union(par, md, o1);
+                    if (r0) lds_link(par, md, o0);
+                    if (r1) lds_link(par, md, o1);
                 }
                 if (fg) md = lds_root(par, md);
                 if (isS) lds_st(pn, md);
@@ -508,12 +524,18 @@ __device__ __forceinline__ void sweep_band(uint32_t *par, uint16_t *cr, const ui
 }
 
 // Merge tile row r with an earlier tile row ru that touches it (the row
-// above for a band seam, the same row of the previous slice in 3D), with
-// general unions (any forest state).
+// above for a band seam, the same row of the previous slice in 3D); any
+// forest state.  JOIN is lds_union (find both roots first) or lds_link
+// (join by stepping up both paths); which is faster depends on how deep the
+// trees are (measured: link for 2D band seams, union for 3D slices).
 // `base` / `base_u`: first node of row r / ru.
-template <bool CONN8>
+template <bool CONN8, bool LINK = false>
 __device__ __forceinline__ void merge_rows(uint32_t *par, const uint64_t *msk, int r, int ru,
                                            uint32_t base, uint32_t base_u) {
+    auto join = [&](uint32_t a, uint32_t b) {
+        if (LINK) lds_link(par, a, b);
+        else lds_union(par, a, b);
+    };
     const uint64_t d = uniform64(msk[r]), u = uniform64(msk[ru]);
     const uint64_t S = run_starts(d), Su = run_starts(u);
     const bool isS = lane_in(S);
@@ -524,11 +546,11 @@ __device__ __forceinline__ void merge_rows(uint32_t *par, const uint64_t *msk, i
     if (CONN8) {
         // PL: upper run containing j-1 (rank = starts at or below j-1, minus 1);
         // PM / PR: upper run starting at j / j+1 (rank = starts below j)
-        if (lane_in(p.pl)) lds_union(par, node, up + bu - 1u);
-        else if (lane_in(p.pm)) lds_union(par, node, up + bu);
-        if (lane_in(p.pr)) lds_union(par, node, up + bu);
+        if (lane_in(p.pl)) join(node, up + bu - 1u);
+        else if (lane_in(p.pm)) join(node, up + bu);
+        if (lane_in(p.pr)) join(node, up + bu);
     } else {
-        if (lane_in(p.pm)) lds_union(par, node, up + bu - (lane_in(Su) ? 0u : 1u));
+        if (lane_in(p.pm)) join(node, up + bu - (lane_in(Su) ? 0u : 1u));
     }
 }
 
@@ -536,7 +558,7 @@ __device__ __forceinline__ void merge_rows(uint32_t *par, const uint64_t *msk, i
 // the last row of the band above.
 template <bool CONN8>
 __device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, int r, uint32_t rbv) {
-    merge_rows<CONN8>(par, msk, r, r - 1, (uint32_t)__builtin_amdgcn_readlane((int)rbv, r),
+    merge_rows<CONN8, true>(par, msk, r, r - 1, (uint32_t)__builtin_amdgcn_readlane((int)rbv, r),
                       (uint32_t)__builtin_amdgcn_readlane((int)rbv, r - 1));
 }
 
@@ -599,9 +621,21 @@ __device__ __forceinline__ void sweep_band_eq(uint32_t *par, uint8_t *col, uint6
             const bool nL = tL != kNone && tL != md;
             const bool nR = tR != kNone && tR != md;
             if (__ballot(nM || nL || nR)) {
-                if (nM) lds_union(par, tM, md);
-                if (nL) lds_union(par, tL, md);
-                if (nR) lds_union(par, tR, md);
+                // as in the binary sweep: one atomicMin per link, a general
+                // join only where the root was already linked elsewhere (a
+                // lane that finds md there met a duplicate of its own link)
+                uint32_t oM = 0, oL = 0, oR = 0;
+                if (nM) oM = atomicMin(&par[tM], md);
+                if (nL) oL = atomicMin(&par[tL], md);
+                if (nR) oR = atomicMin(&par[tR], md);
+                const bool rM = nM && oM < tM && oM != md;
+                const bool rL = nL && oL < tL && oL != md;
+                const bool rR = nR && oR < tR && oR != md;
+                if (__ballot(rM || rL || rR)) {
+                    if (rM) lds_link(par, md, oM);
+                    if (rL) lds_link(par, md, oL);
+                    if (rR) lds_link(par, md, oR);
+                }
                 if (in) md = lds_root(par, md);
                 if (isS) lds_st(pn, md);
             }
@@ -625,12 +659,12 @@ __device__ __forceinline__ void merge_seam_eq(uint32_t *par, const uint64_t *msk
     const uint64_t S = uniform64(msk[r]), Su = uniform64(msk[r - 1]);
     const uint32_t node = (uint32_t)(r * SPR) + bits_below(S) - (lane_in(S) ? 0u : 1u);
     const uint32_t up = (uint32_t)((r - 1) * SPR) + bits_below(Su) - (lane_in(Su) ? 0u : 1u);
-    if (in && vv == vu) lds_union(par, node, up);
+    if (in && vv == vu) lds_link(par, node, up);
     if (CONN8) {
         const uint32_t vuL = from_left(vu, kOutUp), vuR = from_right(vu, kOutUp);
         const uint32_t upL = from_left(up, kNone), upR = from_right(up, kNone);
-        if (in && vv == vuL) lds_union(par, node, upL);
-        if (in && vv == vuR) lds_union(par, node, upR);
+        if (in && vv == vuL) lds_link(par, node, upL);
+        if (in && vv == vuR) lds_link(par, node, upR);
     }
 }
 

@@ -172,19 +172,24 @@ __global__ void __launch_bounds__(256) k2_boundary3d(Vol v) {
         }
         const bool in = z < v.D && y < v.H && x < v.W;
         const uint32_t lp = in ? at(z, y, x) : 0u;
+        // every neighbour's label first (the loads overlap), then all the
+        // task's merge requests together
+        uint32_t A[NOFF], B[NOFF];
 #pragma unroll
         for (int o = 0; o < NOFF; ++o) {
             const Off d = kBack[o];
-            if (xface && d.dx != (task == kLines ? -1 : 1)) continue;  // wave-uniform
+            const bool dirOk = !xface || d.dx == (task == kLines ? -1 : 1);  // wave-uniform
             const int qz = z + d.dz, qy = y + d.dy, qx = x + d.dx;
             const bool outYZ = qz < z0 || qy < y0 || qy >= y0 + kTY;
             const bool outX = qx < x0 || qx >= x0 + kTileW;
             const bool mine = xface ? (outX && !outYZ) : outYZ;
-            const bool valid = lp != 0u && mine && qz >= 0 && qy >= 0 && qy < v.H && qx >= 0 && qx < v.W;
+            const bool valid = dirOk && lp != 0u && mine && qz >= 0 && qy >= 0 && qy < v.H && qx >= 0 &&
+                               qx < v.W;
             const uint32_t lq = valid ? at(qz, qy, qx) : 0u;
-            uint32_t A[1] = {lp - 1u}, B[1] = {lq != 0u ? lq - 1u : kNone};
-            union_requests<1>(v.labels, v.n, A, B);
+            A[o] = lp - 1u;
+            B[o] = lq != 0u ? lq - 1u : kNone;
         }
+        union_requests<NOFF>(v.labels, v.n, A, B);
     }
 }
 
