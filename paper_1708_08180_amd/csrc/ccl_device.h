@@ -184,31 +184,15 @@ __device__ __forceinline__ uint32_t lds_root(const uint32_t *par, uint32_t x) {
     }
 }
 
-// Join the trees of a and b (Sec. II-A-3): find both roots, link the
-// larger under the smaller.  When the atomicMin finds that b stopped being
-// a root in the meantime, the value it returns is b's new parent and the
-// merge is retried from there, so no concurrent link is ever lost.  For
-// arbitrary nodes (band seams, slice merges).
-__device__ __forceinline__ void lds_union(uint32_t *par, uint32_t a, uint32_t b) {
-    while (true) {
-        a = lds_root(par, a);
-        b = lds_root(par, b);
-        if (a == b) return;
-        if (a > b) { const uint32_t t = a; a = b; b = t; }
-        const uint32_t old = atomicMin(&par[b], a);
-        if (old >= b) return;
-        b = old;
-    }
-}
-
-// The same join without a find first, for two nodes that are normally
-// roots: the atomicMin lowers the larger node's parent to the smaller node
-// and returns the parent it had.  If that was the node itself, a root was
-// linked and the merge is done; otherwise the node is now the smaller
-// one's child, its old parent still has to be joined to it, and the step
-// repeats on that pair.  The larger index of the pair drops every step, so
-// the walk ends; every parent only ever moves to a smaller node connected
-// to it, so no concurrent link is lost.
+// Join the trees of a and b (Sec. II-A-3), the larger index under the
+// smaller, without finding the roots first: the atomicMin lowers the larger
+// node's parent to the smaller node and returns the parent it had.  If that
+// was the node itself, a root was linked and the join is done; otherwise the
+// node is now the smaller one's child, its old parent still has to be joined
+// to it, and the step repeats on that pair.  The larger index of the pair
+// drops every step, so the walk ends; every parent only ever moves to a
+// smaller node connected to it, so no concurrent link is lost.  Callers
+// mostly pass roots, which makes this a single atomic.
 __device__ __forceinline__ void lds_link(uint32_t *par, uint32_t a, uint32_t b) {
     while (a != b) {
         if (a > b) { const uint32_t t = a; a = b; b = t; }
@@ -523,19 +507,13 @@ __device__ __forceinline__ void sweep_band(uint32_t *par, uint16_t *cr, const ui
     }
 }
 
-// Merge tile row r with an earlier tile row ru that touches it (the row
-// above for a band seam, the same row of the previous slice in 3D); any
-// forest state.  JOIN is lds_union (find both roots first) or lds_link
-// (join by stepping up both paths); which is faster depends on how deep the
-// trees are (measured: link for 2D band seams, union for 3D slices).
+// Merge tile row r with the row ru above it (a band seam), any forest
+// state; each pair of touching runs is joined once.
 // `base` / `base_u`: first node of row r / ru.
-template <bool CONN8, bool LINK = false>
+template <bool CONN8>
 __device__ __forceinline__ void merge_rows(uint32_t *par, const uint64_t *msk, int r, int ru,
                                            uint32_t base, uint32_t base_u) {
-    auto join = [&](uint32_t a, uint32_t b) {
-        if (LINK) lds_link(par, a, b);
-        else lds_union(par, a, b);
-    };
+    auto join = [&](uint32_t a, uint32_t b) { lds_link(par, a, b); };
     const uint64_t d = uniform64(msk[r]), u = uniform64(msk[ru]);
     const uint64_t S = run_starts(d), Su = run_starts(u);
     const bool isS = lane_in(S);
@@ -558,7 +536,7 @@ __device__ __forceinline__ void merge_rows(uint32_t *par, const uint64_t *msk, i
 // the last row of the band above.
 template <bool CONN8>
 __device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, int r, uint32_t rbv) {
-    merge_rows<CONN8, true>(par, msk, r, r - 1, (uint32_t)__builtin_amdgcn_readlane((int)rbv, r),
+    merge_rows<CONN8>(par, msk, r, r - 1, (uint32_t)__builtin_amdgcn_readlane((int)rbv, r),
                       (uint32_t)__builtin_amdgcn_readlane((int)rbv, r - 1));
 }
 

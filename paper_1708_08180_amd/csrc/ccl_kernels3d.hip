@@ -3,9 +3,10 @@
 //
 //   local merge   one wavefront per slice of the tile sweeps its 16 rows
 //                 with the 2D run union-find (4-connectivity inside a slice
-//                 for 6-connectivity, 8 for 18 and 26); then every row is
-//                 merged with the rows of the previous slice it touches
-//                 (general LDS unions over pair masks).  Every foreground
+//                 for 6-connectivity, 8 for 18 and 26); every run then takes
+//                 its slice root, and every row is joined with the rows of
+//                 the previous slice it touches (pair masks, one LDS
+//                 atomicMin per pair of roots).  Every foreground
 //                 voxel gets labels[p] = 1 + its tile-local root (a dense
 //                 store, as in the paper's Kernel 1), which is already a
 //                 valid forest.
@@ -58,6 +59,36 @@ __device__ __forceinline__ void tile_of(const Vol &v, uint32_t t, int &tx, int &
     tz = (int)(t / (TX * TY));
 }
 
+// Every run node's parent becomes its root (read-only walk; the owner alone
+// stores).  Nodes: 32 slots per tile row, the row's runs first.
+__device__ __forceinline__ void compress_nodes(uint32_t *par, const uint64_t *msk, int tid) {
+    for (int n = tid; n < kRows * kSlotsPerRow; n += 256) {
+        if ((n % kSlotsPerRow) >= __popcll(run_starts(msk[n / kSlotsPerRow]))) continue;
+        const uint32_t root = lds_root(par, (uint32_t)n);
+        if (root != (uint32_t)n) lds_st(&par[n], root);
+    }
+}
+
+// Nodes of the runs of tile row ru that this lane's cell (row mask d) pairs
+// with, at most two (kNone: none): each pair of touching runs is taken by
+// one lane only (pair_masks).  Nodes: 32 slots per row.
+template <bool CONN8>
+__device__ __forceinline__ void upper_runs(uint64_t d, const uint64_t *msk, int ru, uint32_t &q0,
+                                           uint32_t &q1) {
+    const uint64_t u = uniform64(msk[ru]);
+    const uint64_t Su = run_starts(u);
+    const uint32_t up = (uint32_t)(ru * kSlotsPerRow) + bits_below(Su);
+    const PairMasks p = pair_masks<CONN8>(d, u);
+    if (CONN8) {
+        // PL: upper run containing j-1; PM / PR: upper run starting at j / j+1
+        q0 = lane_in(p.pl) ? up - 1u : (lane_in(p.pm) ? up : kNone);
+        q1 = lane_in(p.pr) ? up : kNone;
+    } else {
+        q0 = lane_in(p.pm) ? up - (lane_in(Su) ? 0u : 1u) : kNone;
+        q1 = kNone;
+    }
+}
+
 template <int CONN>
 __global__ void __launch_bounds__(256) k1_local_merge3d(Vol v) {
     constexpr bool CONN8 = CONN != 6;  // neighbours inside a slice
@@ -77,30 +108,63 @@ __global__ void __launch_bounds__(256) k1_local_merge3d(Vol v) {
     // wavefront w sweeps slice w (rows w*16 .. w*16+15)
     sweep_band<kRows, kTY, CONN8>(par, cr, msk, wave, lane, (uint32_t)(lane * kSlotsPerRow));
     __syncthreads();
+    // every run node takes its slice root (read-only walk, owner store), so
+    // the slice merges below start from roots
+    compress_nodes(par, msk, tid);
+    __syncthreads();
     if (wave > 0) {
-        // rows of slice w against the rows of slice w-1 they touch
+        // rows of slice w against the rows of slice w-1 they touch: the
+        // straight row (with diagonals unless 6-connectivity) and, for 18 /
+        // 26, the rows above and below it (straight / with diagonals).  The
+        // roots of all upper runs a lane touches are read together and
+        // joined with its own run's root by one atomicMin each; only a join
+        // whose root was linked elsewhere meanwhile continues as a walk.
+        constexpr int NQ = CONN == 6 ? 1 : 6;
         for (int yi = 0; yi < kTY; ++yi) {
             const int r = wave * kTY + yi, ru = (wave - 1) * kTY + yi;
-            const uint32_t b = (uint32_t)(r * kSlotsPerRow), bu = (uint32_t)(ru * kSlotsPerRow);
+            const uint64_t d = uniform64(msk[r]);
+            const uint64_t S = run_starts(d);
+            const bool fg = lane_in(d);
+            const uint32_t node = (uint32_t)(r * kSlotsPerRow) + bits_below(S) - (lane_in(S) ? 0u : 1u);
+            uint32_t q[NQ];
             if (CONN == 6) {
-                merge_rows<false>(par, msk, r, ru, b, bu);
+                uint32_t none;
+                upper_runs<false>(d, msk, ru, q[0], none);
             } else {
-                merge_rows<true>(par, msk, r, ru, b, bu);
-                // the rows above and below in the previous slice: straight
-                // (18: an edge neighbour) or with diagonals (26: corners too)
-                if (yi > 0) merge_rows<CONN == 26>(par, msk, r, ru - 1, b, bu - kSlotsPerRow);
-                if (yi + 1 < kTY) merge_rows<CONN == 26>(par, msk, r, ru + 1, b, bu + kSlotsPerRow);
+                upper_runs<true>(d, msk, ru, q[0], q[1]);
+                q[2] = q[3] = q[4] = q[5] = kNone;
+                if (yi > 0) upper_runs<CONN == 26>(d, msk, ru - 1, q[2], q[3]);
+                if (yi + 1 < kTY) upper_runs<CONN == 26>(d, msk, ru + 1, q[4], q[5]);
+            }
+            bool want = false;
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) want = want || q[i] != kNone;
+            if (__ballot(fg && want)) {
+                const uint32_t a = fg ? lds_ld(&par[node]) : kNone;
+                uint32_t lo[NQ], o[NQ];
+                bool again[NQ];
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) {
+                    const uint32_t b = q[i] != kNone ? lds_ld(&par[q[i]]) : kNone;
+                    const bool go = fg && b != kNone && b != a;
+                    lo[i] = a < b ? a : b;
+                    const uint32_t hi = a < b ? b : a;
+                    o[i] = go ? atomicMin(&par[hi], lo[i]) : hi;
+                    again[i] = go && o[i] < hi && o[i] != lo[i];
+                }
+                bool any = false;
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) any = any || again[i];
+                if (__ballot(any)) {
+#pragma unroll
+                    for (int i = 0; i < NQ; ++i)
+                        if (again[i]) lds_link(par, lo[i], o[i]);
+                }
             }
         }
     }
     __syncthreads();
-    // every run node finds its root (read-only walk); its owner alone stores
-    // it, so par[] is one step from the root afterwards
-    for (int n = tid; n < kRows * kSlotsPerRow; n += 256) {
-        if ((n % kSlotsPerRow) >= __popcll(run_starts(msk[n / kSlotsPerRow]))) continue;
-        const uint32_t root = lds_root(par, (uint32_t)n);
-        if (root != (uint32_t)n) lds_st(&par[n], root);
-    }
+    compress_nodes(par, msk, tid);
     __syncthreads();
     // dense store: 1 + the global index of every foreground voxel's local root
     const int x = x0 + lane;
