@@ -44,14 +44,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Sources the single-image path is built from: the stored counters hold for
+# its kernels only while these are unchanged.
+PATH_SOURCES = ("ccl_api.cpp", "ccl_device.h", "ccl_internal.h", "ccl_kernels.hip", "ccl_tune.cpp")
+
+
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1708_08180_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in PATH_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -335,8 +335,12 @@ __device__ __forceinline__ void k2_tile_eq(const ImgView &v, uint32_t t) {
 // wavefront.
 constexpr int kFlagCap = 256;
 
+// `rw` / `sl`: the tile's row data and run records in the workspace (they
+// depend on the tile only, so their loads need not wait for the image's
+// descriptor in the batched form).
 template <int TH, int NW, bool EQ>
-__device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *fin, uint16_t *flist) {
+__device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, const uint64_t *rw,
+                                        const uint16_t *sl, uint32_t *fin, uint16_t *flist) {
     static_assert(2 * kTileW + 2 * TH <= kFlagCap, "flagged-root list too small");
     constexpr int SPR = slots_per_row<EQ>();
     constexpr int RPW = TH / NW;
@@ -345,8 +349,7 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t W = (uint32_t)v.W;
-    const uint64_t *rm = v.rowmask + (size_t)t * rowmask_words(TH) + wave * RPW;
-    const uint16_t *sl = v.slots + (size_t)t * TH * SPR;
+    const uint64_t *rm = rw + wave * RPW;
     // global index of the tile's pixel (0, 0); every label fits in 32 bits
     const uint32_t origin = ty * (uint32_t)TH * W + tx * (uint32_t)kTileW;
     // equal-value: every in-image pixel takes part (rows hold run starts)
@@ -360,7 +363,7 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, uint32_t *
     if (EQ) {
         rbv = (uint32_t)((wave * RPW + lane) * SPR);
     } else {
-        const uint16_t *rbg = (const uint16_t *)(v.rowmask + (size_t)t * rowmask_words(TH) + 2 * TH);
+        const uint16_t *rbg = (const uint16_t *)(rw + 2 * TH);
         rbv = lane < RPW ? (uint32_t)rbg[wave * RPW + lane] : 0u;
     }
     uint64_t m[RPW], f[RPW];
@@ -439,7 +442,10 @@ template <int TH, int NW, bool EQ>
 __global__ void __launch_bounds__(NW * 64) k3_link(ImgView v) {
     __shared__ uint32_t fin[TH * kTileW];
     __shared__ uint16_t flist[NW * kFlagCap];
-    k3_tile<TH, NW, EQ>(v, xcd_remap(blockIdx.x, gridDim.x), fin, flist);
+    constexpr int SPR = slots_per_row<EQ>();
+    const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
+    k3_tile<TH, NW, EQ>(v, t, v.rowmask + (size_t)t * rowmask_words(TH), v.slots + (size_t)t * TH * SPR,
+                        fin, flist);
 }
 
 // ------------------------------------------------------------ batch kernels
@@ -509,7 +515,8 @@ __global__ void __launch_bounds__(NW * 64) k3_batch(BatchArgs a) {
     const uint32_t g = xcd_remap(blockIdx.x, gridDim.x);
     if (g >= a.tiles) return;  // workgroup-uniform
     const BatchImage &d = a.descs[a.w.tile_img[g]];
-    k3_tile<TH, NW, false>(batch_view<TH>(d, a.w), g - d.tile_base, fin, flist);
+    k3_tile<TH, NW, false>(batch_view<TH>(d, a.w), g - d.tile_base, a.w.rowmask + (size_t)g * rowmask_words(TH),
+                           a.w.slots + (size_t)g * TH * kSlotsPerRow, fin, flist);
 }
 
 // ---------------------------------------------------------------- launchers

@@ -70,6 +70,20 @@ def test_equal_closed_forms(conn):
         assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("config", EQ_CONFIGS)
+def test_equal_checkerboard_every_config(config):
+    # 4-connectivity: every pixel is its own component, so every edge cell of
+    # every tile is a root that the link pass resolves in the global forest
+    # (the fullest case of the per-wavefront list of such roots: a 64-cell
+    # top row plus the side cells of the band, more than one lane round)
+    H, W = 200, 300
+    cb = wl.checkerboard(H, W, 0, fg=5)
+    say("equal checkerboard %dx%d config=%s" % (H, W, config))
+    got = gpu_label_equal(cb, 4, config=config)
+    assert np.array_equal(got, np.arange(1, H * W + 1, dtype=np.uint32).reshape(H, W))
+    _cmp(cb, 8, config, what="checkerboard")
+
+
 @pytest.mark.parametrize("shape", [(1, 1), (1, 200), (200, 1), (3, 70000 // 64), (129, 65), (64, 64)])
 def test_equal_ragged_and_pitch(shape):
     H, W = shape
