@@ -432,7 +432,10 @@ __global__ void __launch_bounds__(NW * 64) k1_local_merge(ImgView v) {
 
 template <int TH, bool CONN8, bool EQ>
 __global__ void __launch_bounds__(256) k2_boundary(ImgView v, uint32_t tiles) {
-    const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4u + (threadIdx.x >> 6)));
+    // the same XCD-contiguous tile ranges as the local merge and the link:
+    // the forest chains of a region's components stay in one XCD's L2
+    const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)(xcd_remap(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6)));
     if (t >= tiles) return;  // wave-uniform
     if (EQ) k2_tile_eq<TH, CONN8>(v, t);
     else k2_tile<TH, CONN8>(v, t);
@@ -502,7 +505,8 @@ __global__ void __launch_bounds__(NW * 64) k1_batch(BatchArgs a) {
 
 template <int TH, bool CONN8>
 __global__ void __launch_bounds__(256) k2_batch(BatchArgs a) {
-    const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4u + (threadIdx.x >> 6)));
+    const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)(xcd_remap(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6)));
     if (g >= a.tiles) return;  // wave-uniform
     const BatchImage &d = a.descs[a.w.tile_img[g]];
     k2_tile<TH, CONN8>(batch_view<TH>(d, a.w), g - d.tile_base);

@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(256) k2_boundary3d(Vol v) {
     constexpr int NOFF = CONN == 6 ? 3 : (CONN == 18 ? 9 : 13);
     constexpr int kLines = kTY + 2 * (kTZ - 1);  // 22 x-lines per tile
     int tx, ty, tz;
-    tile_of(v, blockIdx.x, tx, ty, tz);
+    tile_of(v, xcd_remap(blockIdx.x, gridDim.x), tx, ty, tz);
     const int lane = lane_id();
     const int wave = (int)(threadIdx.x >> 6);
     const int x0 = tx * kTileW, y0 = ty * kTY, z0 = tz * kTZ;
