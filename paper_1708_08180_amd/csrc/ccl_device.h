@@ -447,7 +447,7 @@ __device__ __forceinline__ PairMasks pair_masks(uint64_t d, uint64_t u, uint64_t
 // atomicMin per lane on its node).  Every other root it touches is then
 // linked under that one; they were roots when the row began, so one
 // atomicMin per link normally does it, and only a link that finds its root
-// already linked elsewhere in this row continues as a general union.  After
+// already linked elsewhere in this row continues as a walk up both trees.  After
 // a row with links the row's roots are re-resolved, so `ra` always holds
 // true roots.
 //
@@ -624,7 +624,7 @@ __device__ __forceinline__ void sweep_band_eq(uint32_t *par, uint8_t *col, uint6
 }
 
 // Band seam for equal-value labeling: the first row r of a band against the
-// last row of the band above (run starts already in msk), general unions.
+// last row of the band above (run starts already in msk), any forest state.
 template <bool CONN8>
 __device__ __forceinline__ void merge_seam_eq(uint32_t *par, const uint64_t *msk, const uint8_t *pix,
                                               int r, int lane, int wlim, int hlim) {
