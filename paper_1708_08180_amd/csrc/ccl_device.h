@@ -267,28 +267,29 @@ __device__ __forceinline__ void union_requests(uint32_t *L, uint32_t n, const ui
     uint64_t pend[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) pend[s] = __ballot(B[s] != kNone);
-    uint32_t ma = kNone, mb = kNone;
-    int cnt = 0;
+    bool more = true;
+    while (more) {  // rounds of up to 64 distinct pairs, one per lane
+        more = false;
+        uint32_t ma = kNone, mb = kNone;
+        int cnt = 0;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        while (pend[s]) {
-            const int lead = __builtin_ctzll(pend[s]);
-            const uint32_t PA = (uint32_t)__builtin_amdgcn_readlane((int)A[s], lead);
-            const uint32_t PB = (uint32_t)__builtin_amdgcn_readlane((int)B[s], lead);
-            if (lane == cnt) {
-                ma = PA;
-                mb = PB;
-            }
+        for (int s = 0; s < NS; ++s) {
+            while (pend[s] && cnt < 64) {
+                const int lead = __builtin_ctzll(pend[s]);
+                const uint32_t PA = (uint32_t)__builtin_amdgcn_readlane((int)A[s], lead);
+                const uint32_t PB = (uint32_t)__builtin_amdgcn_readlane((int)B[s], lead);
+                if (lane == cnt) {
+                    ma = PA;
+                    mb = PB;
+                }
 #pragma unroll
-            for (int q = s; q < NS; ++q) pend[q] &= ~__ballot(A[q] == PA && B[q] == PB);
-            if (++cnt == 64) {
-                g_union(L, n, ma, mb);
-                ma = mb = kNone;
-                cnt = 0;
+                for (int q = s; q < NS; ++q) pend[q] &= ~__ballot(A[q] == PA && B[q] == PB);
+                ++cnt;
             }
+            more = more || pend[s] != 0ull;
         }
+        g_union(L, n, ma, mb);  // one call site: lanes without a pair return at once
     }
-    if (mb != kNone) g_union(L, n, ma, mb);
 }
 
 // Root of x once no link is made any more (link phase).
