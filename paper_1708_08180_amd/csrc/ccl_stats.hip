@@ -124,6 +124,28 @@ __device__ __forceinline__ void add_global(ccl_component &r, uint32_t len, uint3
     atomicAdd((unsigned long long *)&r.sum_y, (unsigned long long)syv);
 }
 
+// Reductions over the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
+    return v;
+}
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o, 64);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o, 64);
+        v += ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
 // Record index of the component whose root pixel is r (its label - 1).
 __device__ __forceinline__ uint32_t record_of(uint32_t r, uint32_t W, uint32_t WW,
                                               const uint64_t *mask, const uint32_t *base) {
@@ -159,41 +181,81 @@ __global__ void __launch_bounds__(kAccWaves * 64) st_accum(const uint32_t *L, ui
     const uint32_t n = H * W;
     const uint32_t x = x0 + (uint32_t)lane;
     const bool xin = x < W;
+    // Adds one run (or a wave's partial record) to the LDS table.
+    auto add_lds = [&](uint32_t l, uint32_t len, uint32_t xa, uint32_t xb, uint32_t ya, uint32_t yb,
+                       uint64_t sxv, uint64_t syv) {
+        uint32_t h = (l * 2654435761u) >> 22;  // 10 bits
+        for (int probe = 0; probe < 16; ++probe) {
+            const uint32_t kk = atomicCAS(&key[h], kEmpty, l);
+            if (kk == kEmpty || kk == l) {
+                atomicAdd(&area[h], len);
+                atomicMin(&xmn[h], xa);
+                atomicMax(&xmx[h], xb);
+                atomicMin(&ymn[h], ya);
+                atomicMax(&ymx[h], yb);
+                atomicAdd(&sx[h], (unsigned long long)sxv);
+                atomicAdd(&sy[h], (unsigned long long)syv);
+                return;
+            }
+            h = (h + 1u) & (uint32_t)(kAccSlots - 1);
+        }
+        // table full around h: straight to the record
+        const uint32_t id = record_of(l - 1u, W, WW, mask, base);
+        if (id < cap) add_global(out[id], len, xa, xb, ya, yb, sxv, syv);
+    };
+    // A large component has runs in most rows, which would all meet on one
+    // table slot: the runs of the wavefront's "hot" label (the smallest
+    // label starting a run in its first row with one, which is a large
+    // component's in noise) add into per-lane registers instead, reduced
+    // over the wavefront once at the end.
+    uint32_t hot = kEmpty;
+    uint32_t hA = 0u, hXa = 0xFFFFFFFFu, hXb = 0u, hYa = 0xFFFFFFFFu, hYb = 0u;
+    uint64_t hSx = 0ull, hSy = 0ull;
+    // all the wavefront's rows are loaded first, so the loads overlap
+    uint32_t lv[kAccRowsPerWave];
+#pragma unroll
+    for (int k = 0; k < kAccRowsPerWave; ++k) {
+        const uint32_t y = y0 + (uint32_t)(wave * kAccRowsPerWave + k);
+        lv[k] = xin && y < H ? L[y * W + x] : 0u;
+    }
+#pragma unroll
     for (int k = 0; k < kAccRowsPerWave; ++k) {
         const uint32_t y = y0 + (uint32_t)(wave * kAccRowsPerWave + k);
         if (y >= H) break;  // wave-uniform
-        const uint32_t l = xin ? L[y * W + x] : 0u;
+        const uint32_t l = lv[k];
         const uint32_t ll = from_left(l, 0u), lr = from_right(l, 0u);
-        const uint64_t S = __ballot(l != 0u && l != ll);
+        const bool start = l != 0u && l != ll && l <= n;  // (labels above H*W: not canonical)
+        const uint64_t S = __ballot(start);
         const uint64_t E = __ballot(l != 0u && l != lr);
-        if (!lane_in(S) || l > n) continue;  // (labels above H*W: not a canonical labeling)
+        if (hot == kEmpty && S) hot = wave_min_u32(start ? l : kEmpty);  // wave-uniform
+        if (!start) continue;
         // this lane starts a run of equal labels; it ends at the first run
         // end at or after it
         const uint32_t e = (uint32_t)lane + (uint32_t)__builtin_ctzll(E >> lane);
         const uint32_t len = e - (uint32_t)lane + 1u, x1 = x0 + e;
         const uint64_t sxv = (uint64_t)len * ((uint64_t)x + (uint64_t)x1) / 2u;
         const uint64_t syv = (uint64_t)len * (uint64_t)y;
-        uint32_t h = (l * 2654435761u) >> 22;  // 10 bits
-        bool done = false;
-        for (int probe = 0; probe < 16 && !done; ++probe) {
-            const uint32_t kk = atomicCAS(&key[h], kEmpty, l);
-            if (kk == kEmpty || kk == l) {
-                atomicAdd(&area[h], len);
-                atomicMin(&xmn[h], x);
-                atomicMax(&xmx[h], x1);
-                atomicMin(&ymn[h], y);
-                atomicMax(&ymx[h], y);
-                atomicAdd(&sx[h], (unsigned long long)sxv);
-                atomicAdd(&sy[h], (unsigned long long)syv);
-                done = true;
-            } else {
-                h = (h + 1u) & (uint32_t)(kAccSlots - 1);
-            }
+        if (l == hot) {
+            hA += len;
+            hXa = min(hXa, x);
+            hXb = max(hXb, x1);
+            hYa = min(hYa, y);
+            hYb = max(hYb, y);
+            hSx += sxv;
+            hSy += syv;
+        } else {
+            add_lds(l, len, x, x1, y, y, sxv, syv);
         }
-        if (!done) {  // table full around h: straight to the record
-            const uint32_t id = record_of(l - 1u, W, WW, mask, base);
-            if (id < cap) add_global(out[id], len, x, x1, y, y, sxv, syv);
-        }
+    }
+    if (hot != kEmpty) {  // wave-uniform
+        hA = wave_sum_u32(hA);
+        hXa = wave_min_u32(hXa);
+        hXb = wave_max_u32(hXb);
+        hYa = wave_min_u32(hYa);
+        hYb = wave_max_u32(hYb);
+        hSx = wave_sum_u64(hSx);
+        hSy = wave_sum_u64(hSy);
+        if (lane == 0 && hA != 0u) add_lds(hot, hA, hXa, hXb, hYa, hYb, hSx, hSy);
     }
     __syncthreads();
     for (int i = tid; i < kAccSlots; i += NT) {
