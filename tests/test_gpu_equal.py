@@ -84,6 +84,19 @@ def test_equal_checkerboard_every_config(config):
     _cmp(cb, 8, config, what="checkerboard")
 
 
+@pytest.mark.parametrize("config", EQ_CONFIGS)
+def test_equal_antidiagonals_many_boundary_pairs(config):
+    # value 1 + (x + y) mod 4: under 8-connectivity every anti-diagonal is its
+    # own component, so every top- and left-edge cell of a tile pairs with a
+    # different component across the edge -- more distinct merge requests
+    # than one wavefront holds at once (the dedupe runs in several rounds)
+    H, W = 200, 300
+    yy, xx = np.indices((H, W))
+    img = (1 + (xx + yy) % 4).astype(np.uint8)
+    _cmp(img, 8, config, what="antidiagonals")
+    _cmp(img, 4, config, what="antidiagonals")
+
+
 @pytest.mark.parametrize("shape", [(1, 1), (1, 200), (200, 1), (3, 70000 // 64), (129, 65), (64, 64)])
 def test_equal_ragged_and_pitch(shape):
     H, W = shape
