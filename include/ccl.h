@@ -340,8 +340,9 @@ int ccl_server_destroy(ccl_server *s);
  * The tile configuration of ccl_label_2d is taken from a process-wide table
  * keyed by (size class = floor(log2(H*W)), connectivity); entries come from
  * ccl_autotune or ccl_tuning_load, misses use the built-in default:
- * tile_h 32 with 8 wavefronts below 2^22 pixels, tile_h 64 with 4 from
- * there up. */
+ * tile_h 32 with 4 wavefronts below 2^22 pixels, tile_h 64 with 4 from
+ * there up.  Equal-value labeling, which is not compiled for (32,4), takes
+ * (32,8) below 2^22 pixels instead. */
 
 /* Time every supported tile configuration on the given image (device
  * buffers as in ccl_label_2d; `labels` is overwritten), `reps` calls each,

@@ -45,12 +45,12 @@ void default_config(int H, int W, int conn, int *th, int *nw) {
             return;
         }
     }
-    // built-in choice (measured on MI355X over 256^2 .. 8192^2, noise and
-    // smoothed masks, both connectivities): short tiles with many waves
-    // while the grid is small, 64-row tiles from about 4 Mpixels up
+    // built-in choice (measured on MI355X over 320x240 .. 8192^2, noise and
+    // smoothed masks, both connectivities): 32-row tiles while the grid is
+    // small, 64-row tiles from about 4 Mpixels up, 4 wavefronts each
     if ((int64_t)H * W < ((int64_t)1 << 22)) {
         *th = 32;
-        *nw = 8;
+        *nw = 4;
     } else {
         *th = 64;
         *nw = 4;

@@ -139,7 +139,7 @@ def test_autotune_validation_without_device():
 def test_tuning_table_roundtrip(tmp_path):
     binding.tuning_clear()
     assert binding.tuning_get(4096, 4096, 8) == (64, 4)       # built-in default, large images
-    assert binding.tuning_get(1080, 1920, 8) == (32, 8)       # built-in default, below 2^22 px
+    assert binding.tuning_get(1080, 1920, 8) == (32, 4)       # built-in default, below 2^22 px
     src = tmp_path / "in.jsonl"
     src.write_text('{"class": 24, "conn": 8, "tile_h": 32, "waves": 2, "ms": 0.150000}\n'
                    '{"class": 20, "conn": 4, "tile_h": 16, "waves": 1, "ms": 0.020000}\n')
