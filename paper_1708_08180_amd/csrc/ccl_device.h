@@ -292,10 +292,27 @@ __device__ __forceinline__ void union_requests(uint32_t *L, uint32_t n, const ui
     }
 }
 
-// Root of x once no link is made any more (link phase).
-__device__ __forceinline__ uint32_t g_root(const uint32_t *L, uint32_t x) {
-    uint32_t v = L[x] - 1u;
-    while (v < x) { x = v; v = L[x] - 1u; }
+// Root of x once no link is made any more (link phase).  A long walk (a
+// component threaded through many tiles, such as a one-pixel-wide spiral)
+// then points every node it passed at the root, so the tiles that walk
+// there later stop short; a short one writes nothing.  The stores are the
+// final root, the value every other writer of those entries stores too.
+__device__ __forceinline__ uint32_t g_root(uint32_t *L, uint32_t x0) {
+    uint32_t x = x0, v = L[x] - 1u, steps = 0;
+    while (v < x) {
+        x = v;
+        v = L[x] - 1u;
+        ++steps;
+    }
+    if (steps > 8u) {
+        uint32_t y = x0;
+        while (y > x) {
+            const uint32_t ny = L[y] - 1u;
+            if (ny >= y) break;
+            L[y] = x + 1u;
+            y = ny;
+        }
+    }
     return x;
 }
 
