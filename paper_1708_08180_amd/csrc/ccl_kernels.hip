@@ -417,7 +417,10 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, const uint
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
         const uint32_t val = rec[k] != kNone ? fin[rec[k] & (TH * kTileW - 1)] + 1u : 0u;
-        if (full || (x < W && y0 + k < (uint32_t)v.H)) out[(size_t)k * W] = val;
+        // streaming stores: the output is not read again here, and keeping
+        // it out of the L2 leaves the run records and the forest cached
+        // for the tiles still to run (a stale cached label is an ancestor)
+        if (full || (x < W && y0 + k < (uint32_t)v.H)) __builtin_nontemporal_store(val, &out[(size_t)k * W]);
     }
     __syncthreads();
 }
