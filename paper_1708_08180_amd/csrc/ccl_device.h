@@ -316,22 +316,6 @@ __device__ __forceinline__ uint32_t g_root(uint32_t *L, uint32_t x0) {
     return x;
 }
 
-// The same with full path compression: every root is final, so every path
-// node may be overwritten with the root (plain stores: all writers store
-// the same value).
-__device__ __forceinline__ uint32_t g_find_final(uint32_t *L, uint32_t x) {
-    uint32_t r = x;
-    uint32_t v = L[r] - 1u;
-    while (v < r) { r = v; v = L[r] - 1u; }
-    while (x > r) {
-        const uint32_t nx = L[x] - 1u;
-        if (nx >= x) break;
-        if (nx != r) L[x] = r + 1u;
-        x = nx;
-    }
-    return r;
-}
-
 // ------------------------------------------------------ tile-local labeling
 
 __device__ __forceinline__ uint32_t global_index(const ImgView &v, int tx, int ty, int th,

@@ -15,8 +15,8 @@
 //                 proposed by its later voxel, once); requests are
 //                 deduplicated along a face and merged with the global
 //                 union-find of the 2D path.
-//   link          every voxel is resolved to its root with full path
-//                 compression.
+//   link          every voxel is resolved to its root and stores its final
+//                 label.
 #include <hip/hip_runtime.h>
 
 #include "ccl.h"
@@ -260,7 +260,13 @@ __global__ void __launch_bounds__(256) k2_boundary3d(Vol v) {
 __global__ void __launch_bounds__(256) k3_link3d(uint32_t *L, uint32_t n) {
     const uint64_t p = (uint64_t)blockIdx.x * 256u + threadIdx.x;
     if (p >= n) return;
-    if (L[p] != 0u) (void)g_find_final(L, (uint32_t)p);
+    const uint32_t lp = L[p];
+    if (lp == 0u) return;
+    // the voxel's root (long walks also repoint the nodes they pass), then
+    // its final label as a streaming store: the output is not read again
+    // beyond the other voxels' walks, for which any ancestor will do
+    const uint32_t r = g_root(L, lp - 1u);
+    if (r + 1u != lp) __builtin_nontemporal_store(r + 1u, &L[p]);
 }
 
 }  // namespace
