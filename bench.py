@@ -35,28 +35,48 @@ BYTES_PER_PIXEL_PATH = 5        # algorithmic minimum: 1 B image in + 4 B label 
 PAPER_CONTEXT = {"gpix_s": 4.99, "ms": 3.36, "hardware": "NVIDIA GTX 1070",
                  "image": "binarized lena 4096x4096", "source": "Table II"}
 
-# algorithmic bytes per pixel of each phase (what the phase must move at least)
+# algorithmic bytes per pixel of each phase (what the phase must move at
+# least): the local merge reads the image, the link writes the labels
 PHASE_NAMES = ("k1_local_merge", "k2_boundary", "k3_link")
-PHASE_BYTES_PER_PIXEL = (1.0, 0.0, 5.0)
+PHASE_BYTES_PER_PIXEL = (1.0, 0.0, 4.0)
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Sources the single-image path is built from: the stored counters hold for
-# its kernels only while these are unchanged.
-PATH_SOURCES = ("ccl_api.cpp", "ccl_device.h", "ccl_internal.h", "ccl_kernels.hip", "ccl_tune.cpp")
+def elf_section(path: str, name: str) -> bytes:
+    """Bytes of one section of a 64-bit little-endian ELF file."""
+    import struct
+
+    with open(path, "rb") as f:
+        data = f.read()
+    if data[:4] != b"\x7fELF" or data[4] != 2 or data[5] != 1:
+        raise ValueError("%s is not a 64-bit little-endian ELF file" % path)
+    shoff, = struct.unpack_from("<Q", data, 0x28)
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", data, 0x3A)
+
+    def sh(i):
+        # name, type, flags, addr, offset, size
+        return struct.unpack_from("<IIQQQQ", data, shoff + i * shentsize)
+
+    str_off, str_size = sh(shstrndx)[4], sh(shstrndx)[5]
+    strtab = data[str_off:str_off + str_size]
+    for i in range(shnum):
+        nm, _, _, _, off, size = sh(i)
+        if strtab[nm:strtab.index(b"\0", nm)].decode() == name:
+            return data[off:off + size]
+    raise KeyError("%s has no section %s" % (path, name))
 
 
-def kernel_source_digest() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1708_08180_amd", "csrc")
-    for name in PATH_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode())
-            h.update(f.read())
-    return h.hexdigest()[:16]
+def device_code_digest() -> str:
+    """Digest of the device code the library runs (its .hip_fatbin section):
+    stored counters hold only for the code object they were taken on."""
+    lib = os.path.join(ROOT, "paper_1708_08180_amd", "libccl.so")
+    try:
+        return hashlib.sha256(elf_section(lib, ".hip_fatbin")).hexdigest()[:16]
+    except (OSError, ValueError, KeyError):
+        return "unavailable"
 
 
 # MI355X: 256 CUs x 4 SIMDs at 2.4 GHz; a SIMD issues at most one wave64
@@ -66,8 +86,8 @@ SIMD_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 
 def stored_counters(kernel: str, workload: str):
     """Per-launch HBM bytes and instruction counts from the committed
-    rocprofv3 counter summary, only if it was taken on the current kernel
-    sources (else None)."""
+    rocprofv3 counter summary, only if it was taken on the device code the
+    library holds now (else None)."""
     path = os.path.join(ROOT, "profiles", "counters.json")
     try:
         with open(path) as f:
@@ -75,7 +95,7 @@ def stored_counters(kernel: str, workload: str):
     except (OSError, ValueError):
         return None
     ent = data.get("%s@%s" % (kernel, workload))
-    if not ent or ent.get("source_digest") != kernel_source_digest():
+    if not ent or ent.get("code_digest") != device_code_digest():
         return None
     return ent
 
@@ -384,7 +404,8 @@ def main():
                                         config=(cfg.tile_h, cfg.waves) if cfg else None)
             phase += np.array(ph)
         phase /= n_ph
-        labels = d_lab.cpu().numpy().view(np.uint32)
+        # only the first image's labels are kept (the CPU baseline checks them)
+        labels = d_lab.cpu().numpy().view(np.uint32) if not results else None
         results.append(dict(name=name, img=img, H=H, W=W, ms=ms, wall=wall, calls=calls,
                             phase=phase.tolist(), labels=labels))
         del d_img, d_lab
@@ -392,26 +413,36 @@ def main():
     head = results[0]
     px = head["H"] * head["W"]
     gpix = px / (head["ms"] * 1e-3) / 1e9
-    k = int(np.argmax(head["phase"]))
-    t_k = head["phase"][k] * 1e-3
-    alg = PHASE_BYTES_PER_PIXEL[k] * px
-    achieved = alg / t_k / 1e9
-    ctr = stored_counters(PHASE_NAMES[k], "4096x4096-bern0.5-conn%d" % args.conn) \
-        if (head["H"], head["W"]) == (4096, 4096) and args.config is None else None
-    roofline = {"bound": "hbm", "kernel": PHASE_NAMES[k], "achieved": round(achieved, 2),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": ctr["bytes_per_launch"] if ctr else None,
-                "alg_bytes_per_launch": int(alg),
-                "kernel_ms": round(head["phase"][k], 5)}
-    if ctr:
-        # what actually limits this kernel: instruction issue (counters per
-        # launch from the committed profile, over the live kernel time)
-        roofline["issue"] = {
-            "valu_instr": ctr["valu_instr"], "salu_instr": ctr["salu_instr"],
-            "peak_instr_per_s_each": SIMD_ISSUE_PER_S,
-            "valu_frac": round(ctr["valu_instr"] / t_k / SIMD_ISSUE_PER_S, 4),
-            "salu_frac": round(ctr["salu_instr"] / t_k / SIMD_ISSUE_PER_S, 4)}
-    path_gbs = BYTES_PER_PIXEL_PATH * px / (head["ms"] * 1e-3) / 1e9
+    workload_key = "4096x4096-bern0.5-conn%d" % args.conn
+    use_ctr = (head["H"], head["W"]) == (4096, 4096) and args.config is None \
+        and args.workload == "headline"
+    ctrs = [stored_counters(n, workload_key) if use_ctr else None for n in PHASE_NAMES]
+    # per kernel: its own algorithmic bytes over its live event-timed duration
+    kernels = {}
+    for n, bpp, ms_k, ctr in zip(PHASE_NAMES, PHASE_BYTES_PER_PIXEL, head["phase"], ctrs):
+        alg = bpp * px
+        ms_k = max(ms_k, 1e-6)
+        ent = {"ms": round(ms_k, 5), "alg_bytes_per_pixel": bpp, "alg_bytes": int(alg),
+               "achieved_GBs": round(alg / (ms_k * 1e-3) / 1e9, 2),
+               "frac": round(alg / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "traffic": ctr["bytes_per_launch"] if ctr else None}
+        if ctr:
+            # instruction issue: what bounds the kernels that move few bytes
+            ent["issue"] = {"valu_instr": ctr["valu_instr"], "salu_instr": ctr["salu_instr"],
+                            "valu_frac": round(ctr["valu_instr"] / (ms_k * 1e-3) / SIMD_ISSUE_PER_S, 4),
+                            "salu_frac": round(ctr["salu_instr"] / (ms_k * 1e-3) / SIMD_ISSUE_PER_S, 4)}
+        kernels[n] = ent
+    dominant = PHASE_NAMES[int(np.argmax(head["phase"]))]
+    # the roofline of the call: one ccl_label_2d call (its three kernels,
+    # launched back to back on one stream) must move at least 5 B/px
+    alg_call = BYTES_PER_PIXEL_PATH * px
+    achieved = alg_call / (head["ms"] * 1e-3) / 1e9
+    traffic = sum(c["bytes_per_launch"] for c in ctrs) if all(ctrs) else None
+    roofline = {"bound": "hbm", "kernel": "ccl_label_2d (k1_local_merge + k2_boundary + k3_link)",
+                "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "alg_bytes_per_launch": int(alg_call), "launch_ms": round(head["ms"], 5),
+                "dominant_kernel": dominant, "kernels": kernels}
     out = {
         "metric": "Gpixels/s (4096^2 8-conn) & % HBM roofline",
         "value": round(gpix, 3),
@@ -429,8 +460,6 @@ def main():
                                % (head["H"], head["W"], 20000 + 100 * 5 + 1, args.conn),
                    "tile": (args.config or "library default")},
         "roofline": roofline,
-        "path_hbm": {"alg_bytes_per_pixel": BYTES_PER_PIXEL_PATH, "achieved_GBs": round(path_gbs, 2),
-                     "frac": round(path_gbs / HBM_PEAK_GBS, 4)},
         "phase_ms": {n: round(v, 5) for n, v in zip(PHASE_NAMES, head["phase"])},
         "per_call_ms": {"min": round(min(head["calls"]), 5), "mean": round(statistics.mean(head["calls"]), 5),
                         "median": round(statistics.median(head["calls"]), 5),
@@ -439,11 +468,14 @@ def main():
     }
     if len(results) > 1:
         rates = [r["H"] * r["W"] / (r["ms"] * 1e-3) / 1e9 for r in results]
-        out["workload_set"] = {"name": args.workload, "n": len(results),
+        out["workload_set"] = {"name": args.workload, "n": len(results), "conn": args.conn,
                                "gpix_min": round(min(rates), 3),
                                "gpix_median": round(statistics.median(rates), 3),
                                "gpix_max": round(max(rates), 3),
-                               "cells": {r["name"]: round(v, 3) for r, v in zip(results, rates)}}
+                               "cells": {r["name"]: {"gpix_s": round(v, 3), "ms": round(r["ms"], 5),
+                                                     "shape": [r["H"], r["W"]],
+                                                     "phase_ms": [round(x, 5) for x in r["phase"]]}
+                                         for r, v in zip(results, rates)}}
     if args.workload == "headline":
         out["extensions"] = bench_extensions(head["img"], args.conn, torch, binding)
     if not args.no_cpu_baseline:

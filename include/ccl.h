@@ -90,11 +90,14 @@ int ccl_version(void);
  * stream  hipStream_t (void*), NULL for the null stream.
  *
  * Scratch: a per-(device, stream) workspace (about 1.5 bytes per pixel for
- * the default tiles) is allocated on first use and grown
- * when a larger image arrives on the same stream (growth synchronizes that
- * stream before freeing the old buffer); ccl_shutdown releases it.  Two
- * concurrent calls on the same stream are ordered by the stream; calls on
- * different streams use different workspaces.
+ * the default tiles) is allocated on first use and grown when a larger
+ * image arrives on the same stream.  Both are stream-ordered allocations on
+ * that stream (hipMallocAsync / hipFreeAsync): the old buffer is freed
+ * after the work already enqueued on the stream, and the host does not
+ * wait.  ccl_shutdown releases it.  Calls on the same stream, from any
+ * thread, are ordered by the stream; calls on different streams use
+ * different workspaces.  Callers that must not allocate at all pass their
+ * own workspace to ccl_label_2d_ex.
  * Returns CCL_OK or an error; on error nothing has been enqueued (except
  * CCL_ERR_HIP from a failed launch).
  */
@@ -102,7 +105,9 @@ int ccl_label_2d(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
                  int32_t connectivity, uint32_t *labels, void *stream);
 
 /* Bytes of workspace ccl_label_2d_ex needs for an H x W image with tile
- * configuration cfg (NULL = default).  Writes *bytes; returns a status. */
+ * configuration cfg.  cfg NULL or zeroed: the library's choice, which the
+ * tuning table may make per connectivity; the size then covers both
+ * connectivities.  Writes *bytes; returns a status. */
 int ccl_workspace_size(int32_t H, int32_t W, const ccl_config *cfg, size_t *bytes);
 
 /*
@@ -325,7 +330,10 @@ int ccl_server_submit(ccl_server *s, const uint8_t *img, int32_t H, int32_t W, i
  * receives the count.  Returns the first error the loop met, else CCL_OK. */
 int ccl_server_poll(ccl_server *s, ccl_frame_result *out, int32_t max, int32_t *n_out);
 
-/* Give a finished frame's label slot back for admission. */
+/* Give a finished frame's label slot back for admission.  Only a slot that
+ * an admitted frame holds may be released, once: a slot outside
+ * [0, n_slots) or one that is not held gives CCL_ERR_INVALID_ARG and
+ * changes nothing. */
 int ccl_server_release(ccl_server *s, int32_t slot);
 
 /* Frames submitted and not yet finished. */

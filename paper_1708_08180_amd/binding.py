@@ -187,23 +187,38 @@ def _check_image(img):
         raise ValueError("image rows must be contiguous (stride(1) == 1)")
 
 
+def _check_out(out, img, shape=None):
+    """An output tensor the kernels may write: int32, contiguous, of the
+    input's shape and on the input's device.  Returns `out`, or a new tensor
+    when it is None."""
+    torch = _torch()
+    shape = tuple(img.shape) if shape is None else tuple(shape)
+    if out is None:
+        return torch.empty(shape, dtype=torch.int32, device=img.device)
+    if not isinstance(out, torch.Tensor):
+        raise TypeError("out must be a torch.Tensor")
+    if tuple(out.shape) != shape or out.dtype != torch.int32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor of shape %s" % (shape,))
+    if not out.is_cuda or out.device != img.device:
+        raise ValueError("out must be a device tensor on the input's device (%s)" % img.device)
+    return out
+
+
 def label(img, conn: int = 8, out=None, config=None, stream=None, workspace=None):
     """Label a 2D uint8 device image; returns an int32 tensor holding the
     uint32 labels bit for bit (0 = background, else 1 + min raster index)."""
     torch = _torch()
     _check_image(img)
     H, W = img.shape
-    if out is None:
-        out = torch.empty((H, W), dtype=torch.int32, device=img.device)
-    else:
-        if out.shape != (H, W) or out.dtype != torch.int32 or not out.is_contiguous():
-            raise ValueError("out must be a contiguous int32 tensor of shape (H, W)")
+    out = _check_out(out, img)
     lib = load_library()
     cfg = None
     if config is not None:
         cfg = ctypes.byref(Config(int(config[0]), int(config[1])))
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
+        if not workspace.is_cuda or workspace.device != img.device or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous device tensor on the input's device")
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
     with torch.cuda.device(img.device):
         rc = lib.ccl_label_2d_ex(img.data_ptr(), H, W, _pitch(img), int(conn), out.data_ptr(),
@@ -217,8 +232,7 @@ def label_plain(img, conn: int = 8, out=None, stream=None):
     torch = _torch()
     _check_image(img)
     H, W = img.shape
-    if out is None:
-        out = torch.empty((H, W), dtype=torch.int32, device=img.device)
+    out = _check_out(out, img)
     lib = load_library()
     with torch.cuda.device(img.device):
         rc = lib.ccl_label_2d(img.data_ptr(), H, W, _pitch(img), int(conn), out.data_ptr(),
@@ -234,10 +248,7 @@ def label_equal(img, conn: int = 8, out=None, config=None, stream=None):
     torch = _torch()
     _check_image(img)
     H, W = img.shape
-    if out is None:
-        out = torch.empty((H, W), dtype=torch.int32, device=img.device)
-    elif out.shape != (H, W) or out.dtype != torch.int32 or not out.is_contiguous():
-        raise ValueError("out must be a contiguous int32 tensor of shape (H, W)")
+    out = _check_out(out, img)
     lib = load_library()
     cfg = ctypes.byref(Config(int(config[0]), int(config[1]))) if config else None
     with torch.cuda.device(img.device):
@@ -261,7 +272,8 @@ def component_stats(labels, capacity: int = None, stream=None):
     import numpy as np
 
     torch = _torch()
-    if labels.dim() != 2 or labels.dtype != torch.int32 or not labels.is_contiguous():
+    if not isinstance(labels, torch.Tensor) or labels.dim() != 2 or labels.dtype != torch.int32 \
+            or not labels.is_contiguous() or not labels.is_cuda:
         raise ValueError("labels must be a contiguous 2D int32 CUDA tensor")
     H, W = labels.shape
     lib = load_library()
@@ -288,10 +300,7 @@ def label3d(vol, conn: int = 26, out=None, stream=None):
     if vol.dim() != 3 or vol.dtype != torch.uint8 or not vol.is_cuda or vol.stride(2) != 1:
         raise ValueError("vol must be a 3D uint8 CUDA tensor with unit stride along W")
     D, H, W = vol.shape
-    if out is None:
-        out = torch.empty((D, H, W), dtype=torch.int32, device=vol.device)
-    elif tuple(out.shape) != (D, H, W) or out.dtype != torch.int32 or not out.is_contiguous():
-        raise ValueError("out must be a contiguous int32 tensor of shape (D, H, W)")
+    out = _check_out(out, vol)
     pitch_y = vol.stride(1) if H > 1 else W
     pitch_z = vol.stride(0) if D > 1 else H * pitch_y
     lib = load_library()
@@ -307,8 +316,7 @@ def label_timed(img, conn: int = 8, out=None, config=None, stream=None):
     torch = _torch()
     _check_image(img)
     H, W = img.shape
-    if out is None:
-        out = torch.empty((H, W), dtype=torch.int32, device=img.device)
+    out = _check_out(out, img)
     lib = load_library()
     cfg = ctypes.byref(Config(int(config[0]), int(config[1]))) if config else None
     ms = (ctypes.c_float * 3)()
@@ -364,8 +372,10 @@ class BatchContext:
         for k, (img, out) in enumerate(zip(images, outs)):
             _check_image(img)
             H, W = img.shape
-            if out.shape != (H, W) or out.dtype != _torch().int32 or not out.is_contiguous():
-                raise ValueError("out[%d] must be a contiguous int32 tensor of shape (H, W)" % k)
+            try:
+                _check_out(out, img)
+            except (TypeError, ValueError) as e:
+                raise ValueError("out[%d]: %s" % (k, e)) from None
             arr[k] = ImageDesc(img.data_ptr(), out.data_ptr(), H, W, _pitch(img))
         return arr
 
@@ -455,6 +465,7 @@ class Server:
 
     def submit(self, img, tag: int):
         """Submit a 2D uint8 device tensor (must stay unchanged until done)."""
+        _check_image(img)
         H, W = img.shape
         return load_library().ccl_server_submit(self._h, img.data_ptr(), H, W, _pitch(img), int(tag))
 

@@ -31,24 +31,26 @@ std::map<std::pair<int, hipStream_t>, WsEntry> g_ws;
 }  // namespace
 
 // Workspace owned by the library for (current device, stream); grown on
-// demand.  Growth synchronizes the stream before releasing the old buffer
-// because earlier work on that stream may still read it.
-int stream_workspace(hipStream_t s, size_t need, void **out) {
+// demand.  The buffers are stream-ordered allocations on that stream: the
+// old buffer of a growth is freed in stream order, after the work already
+// enqueued on the stream that reads it, without blocking the host.  `held`
+// receives the cache lock; the caller keeps it until its kernels are
+// enqueued, so no other thread can replace the buffer in between.
+int stream_workspace(hipStream_t s, size_t need, void **out, std::unique_lock<std::mutex> *held) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail_hip(e);
-    std::lock_guard<std::mutex> lk(g_ws_mu);
+    std::unique_lock<std::mutex> lk(g_ws_mu);
     WsEntry &w = g_ws[std::make_pair(dev, s)];
     if (w.bytes < need) {
         if (w.ptr) {
-            e = hipStreamSynchronize(s);
+            e = hipFreeAsync(w.ptr, s);
             if (e != hipSuccess) return fail_hip(e);
-            (void)hipFree(w.ptr);
             w.ptr = nullptr;
             w.bytes = 0;
         }
         size_t bytes = need + need / 4;  // headroom so slowly growing sizes do not reallocate
-        e = hipMalloc(&w.ptr, bytes);
+        e = hipMallocAsync(&w.ptr, bytes, s);
         if (e != hipSuccess) {
             w.ptr = nullptr;
             (void)hipGetLastError();
@@ -57,7 +59,18 @@ int stream_workspace(hipStream_t s, size_t need, void **out) {
         w.bytes = bytes;
     }
     *out = w.ptr;
+    *held = std::move(lk);
     return CCL_OK;
+}
+
+void release_stream_workspace(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find(std::make_pair(dev, s));
+    if (it == g_ws.end()) return;
+    if (it->second.ptr) (void)hipFreeAsync(it->second.ptr, s);
+    g_ws.erase(it);
 }
 
 void release_stream_workspaces() {
@@ -67,8 +80,11 @@ void release_stream_workspaces() {
         int prev = 0;
         (void)hipGetDevice(&prev);
         (void)hipSetDevice(kv.first.first);
+        // the owning stream may no longer exist: wait for the device, then
+        // free in the order of the null stream
         (void)hipDeviceSynchronize();
-        (void)hipFree(kv.second.ptr);
+        (void)hipFreeAsync(kv.second.ptr, nullptr);
+        (void)hipDeviceSynchronize();
         (void)hipSetDevice(prev);
     }
     g_ws.clear();
@@ -140,10 +156,17 @@ int ccl_version(void) { return 10000; }
 int ccl_workspace_size(int32_t H, int32_t W, const ccl_config *cfg, size_t *bytes) {
     if (!bytes || H <= 0 || W <= 0) return CCL_ERR_INVALID_ARG;
     if ((uint64_t)H * (uint64_t)W > 0xFFFFFFFFull) return CCL_ERR_TOO_LARGE;
-    int th = 0, nw = 0;
-    const int rc = resolve_config(H, W, 8, cfg, &th, &nw);
-    if (rc != CCL_OK) return rc;
-    *bytes = ws_layout(H, W, th).total;
+    // without a configuration the tuning table may hold a different tile
+    // height per connectivity: the size covers both
+    size_t most = 0;
+    for (int conn = 4; conn <= 8; conn += 4) {
+        int th = 0, nw = 0;
+        const int rc = resolve_config(H, W, conn, cfg, &th, &nw);
+        if (rc != CCL_OK) return rc;
+        const size_t b = ws_layout(H, W, th).total;
+        most = b > most ? b : most;
+    }
+    *bytes = most;
     return CCL_OK;
 }
 
@@ -159,11 +182,12 @@ int ccl_label_2d_ex(const uint8_t *img, int32_t H, int32_t W, int64_t pitch, int
     const size_t need = ws_layout(H, W, th).total;
     hipStream_t s = (hipStream_t)stream;
     void *ws = workspace;
+    std::unique_lock<std::mutex> held;
     if (ws) {
         if (workspace_bytes < need) return CCL_ERR_WORKSPACE;
         if (((uintptr_t)ws & 255u) != 0) return CCL_ERR_INVALID_ARG;
     } else {
-        rc = stream_workspace(s, need, &ws);
+        rc = stream_workspace(s, need, &ws, &held);
         if (rc != CCL_OK) return rc;
     }
     const ImgView v = make_view(img, H, W, pitch, labels, ws, th);
@@ -189,7 +213,8 @@ int ccl_label_2d_timed(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
     if (rc != CCL_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     void *ws = nullptr;
-    rc = stream_workspace(s, ws_layout(H, W, th).total, &ws);
+    std::unique_lock<std::mutex> held;
+    rc = stream_workspace(s, ws_layout(H, W, th).total, &ws, &held);
     if (rc != CCL_OK) return rc;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipError_t e = hipSuccess;
@@ -198,6 +223,7 @@ int ccl_label_2d_timed(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
         const ImgView v = make_view(img, H, W, pitch, labels, ws, th);
         e = launch_plain(v, th, nw, connectivity, s, ev);
     }
+    held.unlock();
     if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
     for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventElapsedTime(&phase_ms[i], ev[i], ev[i + 1]);
     for (int i = 0; i < 4; ++i)
@@ -227,7 +253,8 @@ int ccl_label_2d_equal(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
     }
     hipStream_t s = (hipStream_t)stream;
     void *ws = nullptr;
-    rc = stream_workspace(s, ws_layout(H, W, th, true).total, &ws);
+    std::unique_lock<std::mutex> held;
+    rc = stream_workspace(s, ws_layout(H, W, th, true).total, &ws, &held);
     if (rc != CCL_OK) return rc;
     const ImgView v = make_view(img, H, W, pitch, labels, ws, th, true);
     const hipError_t e = launch_plain(v, th, nw, connectivity, s, nullptr, true);

@@ -124,6 +124,23 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nb) {
 
 // ------------------------------------------------------------------ helpers
 
+// Image that owns global tile g: the last image whose tile_base is <= g,
+// i.e. the number of bases <= g minus one.  First among the coarse bases
+// (every 64th image), then among the 64 images of that group; each lane
+// compares one base.
+__device__ __forceinline__ uint32_t batch_image_of(const BatchArgs &a, uint32_t g) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t nc = (a.n + 63u) >> 6;
+    uint32_t cnt = 0;
+    for (uint32_t j = 0; j < nc; j += 64) {
+        const uint32_t k = j + lane;
+        cnt += (uint32_t)__popcll(__ballot(k < nc && a.coarse[k] <= g));
+    }
+    const uint32_t k = ((cnt - 1u) << 6) + lane;
+    return ((cnt - 1u) << 6) + (uint32_t)__popcll(__ballot(k < a.n && a.tile_base[k] <= g)) - 1u;
+}
+
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
 // Smallest s <= j such that bits s..j of m are all set (bit j must be set).
@@ -259,10 +276,11 @@ __device__ __forceinline__ void g_union(uint32_t *L, uint32_t n, uint32_t a, uin
 // Merge requests of one wavefront: every lane holds NS (a, b) slots (b ==
 // kNone: empty).  Along a tile edge most requests repeat the same pair of
 // tile-local roots, so the distinct pairs are collected first (one per
-// lane, at most 64 at a time) and then merged by all lanes concurrently.
-template <int NS>
-__device__ __forceinline__ void union_requests(uint32_t *L, uint32_t n, const uint32_t (&A)[NS],
-                                               const uint32_t (&B)[NS]) {
+// lane, at most 64 at a time) and then merged by all lanes concurrently
+// with join(a, b) (a lane without a pair gets kNone for both).
+template <int NS, class Union>
+__device__ __forceinline__ void union_requests(const uint32_t (&A)[NS], const uint32_t (&B)[NS],
+                                               Union &&join) {
     const int lane = (int)(threadIdx.x & 63);
     uint64_t pend[NS];
 #pragma unroll
@@ -288,7 +306,7 @@ __device__ __forceinline__ void union_requests(uint32_t *L, uint32_t n, const ui
             }
             more = more || pend[s] != 0ull;
         }
-        g_union(L, n, ma, mb);  // one call site: lanes without a pair return at once
+        join(ma, mb);  // one call site: lanes without a pair return at once
     }
 }
 
@@ -344,8 +362,8 @@ __device__ __forceinline__ uint32_t nonzero_bytes16(uint4 b) {
 // 16 pixels of one tile row: row `row` of tile (tx, ty), columns
 // [16q, 16q + 16).  One 16-byte load when the chunk is aligned and inside
 // the image, byte loads with zero fill otherwise.
-__device__ __forceinline__ uint4 load_chunk(const ImgView &v, int tx, int ty, int th, int row,
-                                            int q) {
+template <class V>
+__device__ __forceinline__ uint4 load_chunk(const V &v, int tx, int ty, int th, int row, int q) {
     const int y = ty * th + row;
     const int x = tx * kTileW + q * 16;
     uint4 b = make_uint4(0u, 0u, 0u, 0u);

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "ccl.h"
 #include "ccl_device.h"
 
@@ -63,8 +65,11 @@ inline WsLayout ws_layout(int H, int W, int th, bool equal = false) {
 // Shared by the entry points.
 int fail_hip(hipError_t e);
 // The library's workspace for (current device, stream), at least `need`
-// bytes (grown on demand; growth synchronizes the stream).
-int stream_workspace(hipStream_t s, size_t need, void **out);
+// bytes (grown on demand, in stream order).  *held receives the cache lock,
+// to be kept until the kernels that use the buffer are enqueued.
+int stream_workspace(hipStream_t s, size_t need, void **out, std::unique_lock<std::mutex> *held);
+// Frees the cached workspace of (current device, s), in stream order on s.
+void release_stream_workspace(hipStream_t s);
 int validate_image(const void *img, int32_t H, int32_t W, int64_t pitch, const void *labels);
 int resolve_config(int H, int W, int conn, const ccl_config *cfg, int *th, int *nw);
 void default_config(int H, int W, int conn, int *th, int *nw);

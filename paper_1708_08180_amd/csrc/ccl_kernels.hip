@@ -252,7 +252,7 @@ __device__ __forceinline__ void k2_tile(const ImgView &v, uint32_t t) {
         B[3] = lane_in(p.pr) ? bLr : kNone;
         A[2] = A[3] = aL;
     }
-    union_requests<4>(v.labels, v.n, A, B);
+    union_requests<4>(A, B, [&](uint32_t a, uint32_t b) { g_union(v.labels, v.n, a, b); });
 }
 
 // Equal-value boundary analysis for tile t: like k2_tile, but a pair of
@@ -313,7 +313,7 @@ __device__ __forceinline__ void k2_tile_eq(const ImgView &v, uint32_t t) {
     B[3] = vC == vN ? rL : kNone;
     B[4] = CONN8 && vC == vNu ? bLu : kNone;
     B[5] = CONN8 && vC == vNd ? bLd : kNone;
-    union_requests<6>(v.labels, v.n, A, B);
+    union_requests<6>(A, B, [&](uint32_t a, uint32_t b) { g_union(v.labels, v.n, a, b); });
 }
 
 // ----------------------------------------------------------------- link
@@ -455,22 +455,6 @@ __global__ void __launch_bounds__(NW * 64) k3_link(ImgView v) {
 }
 
 // ------------------------------------------------------------ batch kernels
-
-// Image that owns global tile g: the last image whose tile_base is <= g,
-// i.e. the number of bases <= g minus one.  First among the coarse bases
-// (every 64th image), then among the 64 images of that group; each lane
-// compares one base.
-__device__ __forceinline__ uint32_t batch_image_of(const BatchArgs &a, uint32_t g) {
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t nc = (a.n + 63u) >> 6;
-    uint32_t cnt = 0;
-    for (uint32_t j = 0; j < nc; j += 64) {
-        const uint32_t k = j + lane;
-        cnt += (uint32_t)__popcll(__ballot(k < nc && a.coarse[k] <= g));
-    }
-    const uint32_t k = ((cnt - 1u) << 6) + lane;
-    return ((cnt - 1u) << 6) + (uint32_t)__popcll(__ballot(k < a.n && a.tile_base[k] <= g)) - 1u;
-}
 
 template <int TH>
 __device__ __forceinline__ ImgView batch_view(const BatchImage &b, const BatchWs &w) {

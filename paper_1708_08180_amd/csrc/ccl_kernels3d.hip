@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(256) k2_boundary3d(Vol v) {
             A[o] = lp - 1u;
             B[o] = lq != 0u ? lq - 1u : kNone;
         }
-        union_requests<NOFF>(v.labels, v.n, A, B);
+        union_requests<NOFF>(A, B, [&](uint32_t a, uint32_t b) { g_union(v.labels, v.n, a, b); });
     }
 }
 

@@ -59,7 +59,9 @@ struct ccl_server {
     int dev = 0;
     int64_t slot_pixels = 0;
     uint32_t *slot_mem = nullptr;
+    int32_t n_slots = 0;
     std::vector<int32_t> free_slots;
+    std::vector<uint8_t> held;     // per slot: admitted and not yet released
     std::vector<Worker> workers;
     std::mutex mu;
     std::condition_variable cv;
@@ -104,6 +106,7 @@ void run_loop(ccl_server *s) {
                 s->arrivals.pop_front();
                 f.slot = s->free_slots.back();
                 s->free_slots.pop_back();
+                s->held[(size_t)f.slot] = 1;
                 f.d.labels = s->slot_mem + (size_t)f.slot * (size_t)s->slot_pixels;
                 f.t_admit = now_ns();
                 s->admitted.push_back(f);
@@ -172,6 +175,9 @@ void run_loop(ccl_server *s) {
 void destroy_server(ccl_server *s) {
     for (Worker &w : s->workers) {
         if (w.stream) (void)hipStreamSynchronize(w.stream);
+        // plain mode labels through ccl_label_2d, whose workspace is cached
+        // per stream: that stream is about to go away
+        if (w.stream) release_stream_workspace(w.stream);
         if (w.ctx) (void)ccl_ctx_destroy(w.ctx);
         if (w.done) (void)hipEventDestroy(w.done);
         if (w.stream) (void)hipStreamDestroy(w.stream);
@@ -201,7 +207,8 @@ int ccl_server_create(ccl_server **out, const ccl_server_opts *o) {
         return fail_hip(e);
     }
     s->slot_pixels = (int64_t)align_up((size_t)o->max_frame_pixels, 64);
-    const int64_t n_slots = o->hbm_budget / (s->slot_pixels * (int64_t)sizeof(uint32_t));
+    int64_t n_slots = o->hbm_budget / (s->slot_pixels * (int64_t)sizeof(uint32_t));
+    if (n_slots > 0x7FFFFFFF) n_slots = 0x7FFFFFFF;
     if (n_slots < 1) {
         delete s;
         return CCL_ERR_CAPACITY;
@@ -212,6 +219,8 @@ int ccl_server_create(ccl_server **out, const ccl_server_opts *o) {
         delete s;
         return CCL_ERR_OUT_OF_MEMORY;
     }
+    s->n_slots = (int32_t)n_slots;
+    s->held.assign((size_t)n_slots, 0);
     for (int64_t i = n_slots - 1; i >= 0; --i) s->free_slots.push_back((int32_t)i);
     s->workers.resize((size_t)o->n_workers);
     for (Worker &w : s->workers) {
@@ -241,7 +250,7 @@ int ccl_server_create(ccl_server **out, const ccl_server_opts *o) {
 
 int ccl_server_slots(const ccl_server *s, int32_t *n_slots) {
     if (!s || !n_slots) return CCL_ERR_INVALID_ARG;
-    *n_slots = (int32_t)(s->opts.hbm_budget / (s->slot_pixels * (int64_t)sizeof(uint32_t)));
+    *n_slots = s->n_slots;
     return CCL_OK;
 }
 
@@ -294,6 +303,10 @@ int ccl_server_release(ccl_server *s, int32_t slot) {
     if (!s || slot < 0) return CCL_ERR_INVALID_ARG;
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        // only a slot that an admitted frame holds goes back to the pool: an
+        // out-of-range or repeated release would hand one slot to two frames
+        if (slot >= s->n_slots || !s->held[(size_t)slot]) return CCL_ERR_INVALID_ARG;
+        s->held[(size_t)slot] = 0;
         s->free_slots.push_back(slot);
     }
     s->cv.notify_one();

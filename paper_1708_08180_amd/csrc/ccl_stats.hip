@@ -288,7 +288,8 @@ extern "C" int ccl_component_stats(const uint32_t *labels, int32_t H, int32_t W,
     if ((uint64_t)H * (uint64_t)W > 0xFFFFFFFFull) return CCL_ERR_TOO_LARGE;
     hipStream_t s = (hipStream_t)stream;
     void *ws = nullptr;
-    int rc = stream_workspace(s, stats_workspace_bytes(H, W), &ws);
+    std::unique_lock<std::mutex> held;
+    int rc = stream_workspace(s, stats_workspace_bytes(H, W), &ws, &held);
     if (rc != CCL_OK) return rc;
     const uint32_t WW = (uint32_t)((W + kTileW - 1) / kTileW);
     const uint32_t words = (uint32_t)H * WW;

@@ -90,11 +90,13 @@ def copy_labels(ptr: int, H: int, W: int) -> np.ndarray:
 
 
 def run(rings, rate: float, duration_s: float, plain: bool, conn: int = 8, n_workers: int = 2,
-        max_batch: int = 8, hbm_budget: int = None, seed: int = 7, check=None, config=None):
+        max_batch: int = 8, hbm_budget: int = None, seed: int = 7, check=None, config=None,
+        check_all: bool = False):
     """Drive one server at an offered load of `rate` frames/s for `duration_s`.
 
     check: optional callable(tag, frame_host, labels_numpy) run after the run
-    on a few frames whose labels are copied out when they complete."""
+    on the frames whose labels are copied out when they complete: about six
+    spread over the run, or every frame with check_all."""
     shapes = [r[0][0].shape for r in rings]
     max_px = max(h * w for h, w in shapes)
     if hbm_budget is None:
@@ -107,7 +109,8 @@ def run(rings, rate: float, duration_s: float, plain: bool, conn: int = 8, n_wor
     lat = []
     done_ts = []
     keep = {}
-    want_check = set(range(0, len(sched), max(1, len(sched) // 6))) if check else set()
+    step = 1 if check_all else max(1, len(sched) // 6)
+    want_check = set(range(0, len(sched), step)) if check else set()
     sub_ts = []
     t0 = time.perf_counter_ns()
     i = 0

@@ -6,8 +6,9 @@ import sys
 
 import numpy as np
 
-CONFIGS = [(64, 4), (64, 8), (64, 16), (64, 1), (32, 2), (32, 4), (32, 8), (16, 1), (16, 4),
-           (16, 16)]
+# every compiled tile configuration (tile_h, waves)
+CONFIGS = [(64, 4), (64, 8), (64, 16), (64, 1), (64, 2), (32, 1), (32, 2), (32, 4), (32, 8),
+           (32, 16), (16, 1), (16, 2), (16, 4), (16, 8), (16, 16)]
 
 
 def say(*a):

@@ -2,13 +2,15 @@
 oracle and the single-image entry point bit for bit, across repeated calls
 (graph replays and node updates, calls queued back to back) and ragged
 image sets."""
+import dataclasses
+
 import numpy as np
 import pytest
 
 import oracle
 from paper_1708_08180_amd import binding
 from paper_1708_08180_amd import workloads as wl
-from tests.gpu_util import say
+from tests.gpu_util import CONFIGS, say
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +54,7 @@ def test_batch_matches_oracle(conn, use_graph):
     ctx.close()
 
 
-@pytest.mark.parametrize("config", [(16, 1), (32, 2), (64, 4), (64, 16)])
+@pytest.mark.parametrize("config", CONFIGS)
 def test_batch_tile_configs(config):
     ctx = binding.BatchContext(16, 16 * 480 * 640, config=config)
     imgs = _mixed_images(16, 9)
@@ -144,3 +146,22 @@ def test_autotune_records_a_supported_config():
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint32), oracle.label(img, 8))
     binding.tuning_clear()
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_batch_mixed_workload_sizes(conn):
+    """Images of the batched workload's recipe and all its sizes, 3840x2160
+    included, checked one by one against the oracle."""
+    specs = wl.batch_spec(10, 40000)
+    sizes = wl.BATCH_SIZES
+    # the recipe's draws, with the sizes set so that every size appears twice
+    specs = [dataclasses.replace(s, H=sizes[k % 5][0], W=sizes[k % 5][1]) for k, s in enumerate(specs)]
+    imgs = wl.batch_images(specs)
+    assert {im.shape for im in imgs} == set(sizes)
+    ctx = binding.BatchContext(len(imgs), sum(im.size for im in imgs))
+    got = _run(ctx, imgs, conn)
+    for k, (im, g) in enumerate(zip(imgs, got)):
+        say("batch mixed image %d %dx%d conn=%d" % (k, im.shape[0], im.shape[1], conn))
+        want = oracle.label(im, conn)
+        assert np.array_equal(g, want), "image %d (%dx%d) differs" % (k, im.shape[0], im.shape[1])
+    ctx.close()

@@ -21,12 +21,19 @@ def rings():
 def _checker(conn, seen):
     import torch
 
+    # ring frames repeat: the oracle and the stand-alone call run once per
+    # distinct frame
+    cache = {}
+
     def check(tag, frame_h, labels):
-        want = oracle.label(frame_h, conn)
+        key = id(frame_h)
+        if key not in cache:
+            alone = binding.label_plain(torch.from_numpy(frame_h).cuda(), conn)
+            torch.cuda.synchronize()
+            cache[key] = (oracle.label(frame_h, conn), alone.cpu().numpy().view(np.uint32))
+        want, alone = cache[key]
         assert np.array_equal(labels, want), "frame %d differs from the oracle" % tag
-        alone = binding.label_plain(torch.from_numpy(frame_h).cuda(), conn)
-        torch.cuda.synchronize()
-        assert np.array_equal(labels, alone.cpu().numpy().view(np.uint32)), "frame %d: mix != alone" % tag
+        assert np.array_equal(labels, alone), "frame %d: mix != alone" % tag
         seen.append(tag)
     return check
 
@@ -59,4 +66,50 @@ def test_serve_shutdown_with_frames_in_flight(rings):
 def test_serve_rejects_oversized_frame(rings):
     srv = binding.Server(240 * 320, 4 * 240 * 320 * 4, n_workers=1, max_batch=2)
     assert srv.submit(rings[2][0][1], 0) == 6       # 480x640 > max_frame_pixels
+    srv.close()
+
+
+@pytest.fixture(scope="module")
+def camera_rings():
+    # the served workload's cameras: 2 x 1920x1080 and 2 x 3840x2160
+    return serve.make_rings(ring=3, seed_base=50000)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_serve_full_size_cameras_every_frame(camera_rings, plain):
+    """Every completed 1080p and 2160p frame equals the oracle and the same
+    frame labeled alone, in the batched mix and in the per-frame loop."""
+    seen = []
+    res = serve.run(camera_rings, rate=800.0, duration_s=0.05, plain=plain, conn=8,
+                    check=_checker(8, seen), check_all=True)
+    say("serve full-size %s: %d frames, all %d checked" % (res.mode, res.frames, len(seen)))
+    assert res.frames >= 10 and len(seen) == res.frames
+    sizes = {camera_rings[c][0][0].shape for c in range(4)}
+    assert sizes == {(1080, 1920), (2160, 3840)}
+
+
+def test_serve_release_rejects_bad_slots(rings):
+    """Only a held slot can be released, once."""
+    srv = binding.Server(480 * 640, 2 * 480 * 640 * 4, n_workers=1, max_batch=2)
+    assert srv.n_slots == 2
+    assert srv.submit(rings[2][0][1], 5) == 0
+    got = []
+    while not got:
+        got = srv.poll()
+    slot = got[0][2]
+    for bad in (-1, 2, 1000, 1 - slot):    # out of range, or the slot no frame holds
+        with pytest.raises(binding.CclError):
+            srv.release(bad)
+    srv.release(slot)
+    with pytest.raises(binding.CclError):   # second release of the same slot
+        srv.release(slot)
+    # the pool still works: both slots admit frames again
+    for t in (6, 7):
+        assert srv.submit(rings[2][0][1], t) == 0
+    done = []
+    while len(done) < 2:
+        done += srv.poll()
+    assert sorted(r[2] for r in done) == [0, 1]
+    for r in done:
+        srv.release(r[2])
     srv.close()
