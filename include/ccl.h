@@ -127,6 +127,27 @@ int ccl_label_2d_ex(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
                     size_t workspace_bytes, const ccl_config *cfg, void *stream);
 
 /*
+ * ccl_label_2d_noalloc -- ccl_label_2d for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, output, kernels and
+ * default tile configuration as ccl_label_2d; the tile workspace is a fixed
+ * array of CCL_NOALLOC_SCRATCH_BYTES in device memory, one per device, held
+ * from the library's load until the process ends.  The call allocates and
+ * frees nothing (its first call on a device looks the array's address up).
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents: calls whose work overlaps on one device (different
+ * streams, or host threads racing on unordered streams) race on it and give
+ * wrong labels; calls ordered on one stream are safe.
+ * Errors: as ccl_label_2d, plus CCL_ERR_WORKSPACE, before anything is
+ * enqueued, when the image needs more workspace than the array holds
+ * (ccl_workspace_size(H, W, NULL) > CCL_NOALLOC_SCRATCH_BYTES; a 4096 x 4096
+ * image fits).
+ */
+#define CCL_NOALLOC_SCRATCH_BYTES (32u << 20)
+int ccl_label_2d_noalloc(const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
+                         int32_t connectivity, uint32_t *labels, void *stream);
+
+/*
  * ccl_label_2d_timed -- ccl_label_2d with a HIP event recorded before,
  * between and after the three phases on `stream`; blocks until the work is
  * done and writes the elapsed milliseconds of phase 1 (local merge), phase 2

@@ -65,6 +65,7 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_size_t)]),
     "ccl_label_2d_ex": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, _P, ctypes.c_size_t,
                                        ctypes.POINTER(Config), _P]),
+    "ccl_label_2d_noalloc": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, _P]),
     "ccl_label_2d_timed": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, ctypes.POINTER(Config), _P,
                                           ctypes.POINTER(ctypes.c_float)]),
     "ccl_label_2d_equal": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, ctypes.POINTER(Config), _P]),
@@ -238,6 +239,22 @@ def label_plain(img, conn: int = 8, out=None, stream=None):
         rc = lib.ccl_label_2d(img.data_ptr(), H, W, _pitch(img), int(conn), out.data_ptr(),
                               _stream_handle(stream))
     _check(rc, "ccl_label_2d")
+    return out
+
+
+def label_noalloc(img, conn: int = 8, out=None, stream=None):
+    """The ccl_label_2d_noalloc entry point: default tiles, workspace in the
+    library's fixed device array (no allocation by the library).  Calls
+    whose work overlaps on one device race on that array."""
+    torch = _torch()
+    _check_image(img)
+    H, W = img.shape
+    out = _check_out(out, img)
+    lib = load_library()
+    with torch.cuda.device(img.device):
+        rc = lib.ccl_label_2d_noalloc(img.data_ptr(), H, W, _pitch(img), int(conn), out.data_ptr(),
+                                      _stream_handle(stream))
+    _check(rc, "ccl_label_2d_noalloc")
     return out
 
 

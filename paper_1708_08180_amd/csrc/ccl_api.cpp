@@ -109,7 +109,7 @@ int resolve_config(int H, int W, int conn, const ccl_config *cfg, int *th, int *
 }
 
 ImgView make_view(const uint8_t *img, int32_t H, int32_t W, int64_t pitch, uint32_t *labels,
-                  void *ws, int th, bool equal = false) {
+                  void *ws, int th, bool equal) {
     const WsLayout l = ws_layout(H, W, th, equal);
     ImgView v;
     v.img = img;

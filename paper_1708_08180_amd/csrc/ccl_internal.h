@@ -73,5 +73,9 @@ void release_stream_workspace(hipStream_t s);
 int validate_image(const void *img, int32_t H, int32_t W, int64_t pitch, const void *labels);
 int resolve_config(int H, int W, int conn, const ccl_config *cfg, int *th, int *nw);
 void default_config(int H, int W, int conn, int *th, int *nw);
+// The kernels' view of one image whose workspace (ws_layout(H, W, th,
+// equal).total bytes, 256-byte aligned) starts at ws.
+ImgView make_view(const uint8_t *img, int32_t H, int32_t W, int64_t pitch, uint32_t *labels,
+                  void *ws, int th, bool equal = false);
 
 }  // namespace ccl

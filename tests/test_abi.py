@@ -157,3 +157,30 @@ def test_tuning_table_roundtrip(tmp_path):
         binding.tuning_load(str(bad))
     binding.tuning_clear()
     assert binding.tuning_get(4096, 4096, 8) == (64, 4)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, 4, 4, 4, 8, FAKE, None), 1),        # null image
+    ((FAKE, 4, 4, 4, 8, None, None), 1),        # null labels
+    ((FAKE, 0, 4, 4, 8, FAKE, None), 1),        # H = 0
+    ((FAKE, 4, 8, 7, 8, FAKE, None), 1),        # pitch < W
+    ((FAKE, 4, 4, 4, 6, FAKE, None), 2),        # connectivity 6
+    ((FAKE, 65536, 65537, 65537, 8, FAKE, None), 3),  # H*W > 2^32-1
+    ((FAKE, 8192, 8192, 8192, 8, FAKE, None), 7),     # needs more than the fixed array
+    ((FAKE, 1, 60000000, 60000000, 4, FAKE, None), 7),
+])
+def test_noalloc_invalid_arguments(args, code):
+    """The fixed-workspace entry point rejects bad arguments, and images
+    whose workspace exceeds its array, before any HIP call."""
+    lib = binding.load_library()
+    assert lib.ccl_label_2d_noalloc(*args) == code
+
+
+def test_noalloc_limit_covers_4096_square():
+    lib = binding.load_library()
+    size = ctypes.c_size_t(0)
+    assert lib.ccl_workspace_size(4096, 4096, None, ctypes.byref(size)) == 0
+    limit = 32 << 20
+    assert 0 < size.value <= limit
+    assert lib.ccl_workspace_size(8192, 8192, None, ctypes.byref(size)) == 0
+    assert size.value > limit
