@@ -61,7 +61,8 @@ typedef enum ccl_status {
  * 64-lane wavefront spans a tile row) and tile_h rows tall; each workgroup
  * runs `waves` wavefronts, each owning tile_h / waves consecutive rows.
  * Supported pairs: tile_h in {16, 32, 64}; waves in {1, 2, 4, 8, 16} with
- * waves <= tile_h.  A zeroed struct or a NULL pointer selects the default. */
+ * tile_h / waves >= 2 (the binary local merge gives every wavefront whole
+ * two-row bands).  A zeroed struct or a NULL pointer selects the default. */
 typedef struct ccl_config {
     int32_t tile_h;
     int32_t waves;

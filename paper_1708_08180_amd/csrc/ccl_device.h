@@ -50,8 +50,11 @@ constexpr int kSlotsPerRow = slots_per_row<false>();
 
 __host__ __device__ constexpr int roots_per_tile(int th) { return 2 * kTileW + 2 * th; }
 // 64-bit words per tile of the row data: TH row masks, TH edge-root masks,
-// then TH 16-bit row bases (first record of every row)
-__host__ __device__ constexpr int rowmask_words(int th) { return 2 * th + th / 4; }
+// TH / 2 band interval-end masks, then TH / 2 16-bit band bases (first
+// record of every band)
+__host__ __device__ constexpr int rowmask_words(int th) { return 2 * th + th / 2 + th / 8; }
+__host__ __device__ constexpr int rowmask_ends(int th) { return 2 * th; }
+__host__ __device__ constexpr int rowmask_bases(int th) { return 2 * th + th / 2; }
 __host__ __device__ constexpr int roots_top(int) { return 0; }
 __host__ __device__ constexpr int roots_bottom(int) { return kTileW; }
 __host__ __device__ constexpr int roots_left(int) { return 2 * kTileW; }
@@ -558,6 +561,152 @@ template <bool CONN8>
 __device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, int r, uint32_t rbv) {
     merge_rows<CONN8>(par, msk, r, r - 1, (uint32_t)__builtin_amdgcn_readlane((int)rbv, r),
                       (uint32_t)__builtin_amdgcn_readlane((int)rbv, r - 1));
+}
+
+// ------------------------------------------------- two-row band nodes
+//
+// The binary local merge takes the tile two rows at a time.  Inside such a
+// band every connected component is one contiguous interval of columns:
+// under 8-connectivity the intervals are the runs of t | b (t the band's top
+// row, b its bottom row); under 4-connectivity they are those runs split
+// wherever neither row continues across the column boundary.  So the row
+// scan and the row-column unification of Sec. II-A-2 reduce to a few 64-bit
+// operations per band, and the union-find of Sec. II-A-3 runs over intervals
+// and over half as many steps as rows.
+//
+// Node n of a tile is its n-th interval in band order, left to right inside
+// a band.  Every parent entry holds a key, the node's smallest pixel (tile
+// row << 6 | column) above its node number: an atomicMin on keys links the
+// tree whose node holds the larger pixel under the other, so the root of
+// every tree is the node holding the component's smallest pixel (the
+// linking rule of Sec. II-A-3, with pixels as the order).  A root's entry is
+// its own key.
+
+constexpr uint32_t kNodeBits = 11;  // at most 2048 nodes per tile (64 intervals per band)
+constexpr uint32_t kNodeMask = (1u << kNodeBits) - 1u;
+
+// First column of every interval of the band (t above b).
+template <bool CONN8>
+__device__ __forceinline__ uint64_t band_starts(uint64_t t, uint64_t b) {
+    const uint64_t m = t | b;
+    uint64_t s = m & ~(m << 1);
+    if (!CONN8) s |= m & (m << 1) & ~(t & (t << 1)) & ~(b & (b << 1));
+    return s;
+}
+
+// Last column of every interval, from the band's columns m = t | b and the
+// interval starts s.
+__device__ __forceinline__ uint64_t band_ends(uint64_t m, uint64_t s) { return m & (~(m >> 1) | (s >> 1)); }
+
+// Root key of the tree holding key k (read-only walk; see lds_root).
+__device__ __forceinline__ uint32_t key_root(const uint32_t *par, uint32_t k) {
+    while (true) {
+        const uint32_t p = lds_ld(&par[k & kNodeMask]);
+        if (p >= k) return k;
+        k = p;
+    }
+}
+
+// Join the trees of the nodes with keys a and b (or of any of their
+// ancestors), as lds_link does with node numbers.
+__device__ __forceinline__ void key_link(uint32_t *par, uint32_t a, uint32_t b) {
+    while (a != b) {
+        if (a > b) { const uint32_t t = a; a = b; b = t; }
+        const uint32_t old = atomicMin(&par[b & kNodeMask], a);
+        if (old >= b) return;
+        b = old;
+    }
+}
+
+// Sweep of one wavefront's bands, top to bottom, as sweep_band does for
+// rows: `ra` carries per lane the root key of the interval holding the
+// pixel above the band's top row (kNone for background); a band's
+// interval takes the smallest root its top row touches (one LDS atomicMin
+// per lane on its node), every other touched root is linked under it, and
+// the bottom row's pixels hand the interval's root on to the next band.
+// The first node of band j is lane j's value of `bbv`; ends[j] holds the
+// band's interval ends.  Touching pairs come from pair_masks over the top
+// row and the row above; several of them may name the same two intervals.
+template <int BPW, bool CONN8>
+__device__ __forceinline__ void sweep_bands(uint32_t *par, const uint64_t *msk, const uint64_t *ends,
+                                            int wave, int lane, uint32_t bbv) {
+    uint32_t ra = kNone;
+    uint64_t u = 0;
+    uint64_t m[2 * BPW], e[BPW];
+#pragma unroll
+    for (int k = 0; k < 2 * BPW; ++k) m[k] = uniform64(msk[wave * 2 * BPW + k]);
+#pragma unroll
+    for (int k = 0; k < BPW; ++k) e[k] = uniform64(ends[wave * BPW + k]);
+#pragma unroll
+    for (int k = 0; k < BPW; ++k) {
+        const int band = wave * BPW + k;
+        const uint64_t t = m[2 * k], b = m[2 * k + 1];
+        const uint64_t M = t | b, E = e[k];
+        const uint64_t S = band_starts<CONN8>(t, b);
+        const bool in = lane_in(M);
+        const uint32_t rb = (uint32_t)__builtin_amdgcn_readlane((int)bbv, band);
+        const uint32_t node = bits_below_plus(E, rb);
+        uint32_t *pn = &par[node];
+        if (lane_in(S)) {
+            // the interval's smallest pixel: its first top-row pixel, else
+            // its first bottom-row pixel
+            const uint64_t from = ~0ull << lane;
+            const uint64_t span = from & ((2ull << __builtin_ctzll(E & from)) - 1ull);
+            const uint64_t tt = t & span;
+            const uint32_t row = (uint32_t)(2 * band) + (tt ? 0u : 1u);
+            const uint32_t col = (uint32_t)__builtin_ctzll(tt ? tt : (b & span));
+            lds_st(pn, (((row << 6) | col) << kNodeBits) | node);
+        }
+        uint32_t md = kNone;
+        if (k > 0) {
+            const PairMasks p = pair_masks<CONN8>(t, u);
+            const uint32_t rL = from_left(ra, kNone), rR = from_right(ra, kNone);
+            const uint32_t t0 = lane_in(p.pm) ? ra : (lane_in(p.pl) ? rL : kNone);
+            const uint32_t t1 = lane_in(p.pr) ? rR : kNone;
+            const uint32_t tm = t0 < t1 ? t0 : t1;
+            if (tm != kNone) atomicMin(pn, tm);
+            if (in) md = lds_ld(pn);
+            const bool n0 = t0 != kNone && t0 != md;
+            const bool n1 = t1 != kNone && t1 != md;
+            if (__ballot(n0 || n1)) {
+                uint32_t o0 = 0, o1 = 0;
+                if (n0) o0 = atomicMin(&par[t0 & kNodeMask], md);
+                if (n1) o1 = atomicMin(&par[t1 & kNodeMask], md);
+                const bool r0 = n0 && o0 < t0 && o0 != md, r1 = n1 && o1 < t1 && o1 != md;
+                if (__ballot(r0 || r1)) {
+                    if (r0) key_link(par, md, o0);
+                    if (r1) key_link(par, md, o1);
+                }
+                if (in) md = key_root(par, md);
+                if (lane_in(S)) lds_st(pn, md);
+            }
+        } else if (in) {
+            md = lds_ld(pn);
+        }
+        ra = lane_in(b) ? md : kNone;
+        u = b;
+    }
+}
+
+// Band seam of a multi-wavefront tile: the top row of band k against the
+// bottom row of band k - 1, any forest state.  bk / bu: first node of band
+// k / k - 1.
+template <bool CONN8>
+__device__ __forceinline__ void merge_band_seam(uint32_t *par, const uint64_t *msk, const uint64_t *ends,
+                                                int k, uint32_t bk, uint32_t bu) {
+    const uint64_t t = uniform64(msk[2 * k]), u = uniform64(msk[2 * k - 1]);
+    const uint64_t E = uniform64(ends[k]), Eu = uniform64(ends[k - 1]);
+    const uint32_t node = bk + bits_below(E);
+    const uint32_t upC = bu + bits_below(Eu);  // interval of the upper cell in this column
+    auto join = [&](uint32_t a, uint32_t b) { key_link(par, lds_ld(&par[a]), lds_ld(&par[b])); };
+    const PairMasks p = pair_masks<CONN8>(t, u);
+    if (CONN8) {
+        if (lane_in(p.pl)) join(node, bu + bits_below(Eu << 1));
+        else if (lane_in(p.pm)) join(node, upC);
+        if (lane_in(p.pr)) join(node, upC + (uint32_t)bit(Eu, (int)(threadIdx.x & 63)));
+    } else {
+        if (lane_in(p.pm)) join(node, upC);
+    }
 }
 
 // ------------------------------------------- equal-value labeling (K1 part)

@@ -190,6 +190,134 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
     __syncthreads();  // LDS may be reused for another tile
 }
 
+// Binary local merge over two-row bands (see sweep_bands).
+template <int TH>
+struct K1BandLds {
+    uint32_t par[TH * kSlotsPerRow];  // node keys (a band has at most 64 intervals)
+    uint64_t msk[TH];                 // per row: foreground mask
+    uint64_t ends[TH / 2];            // per band: interval ends
+    uint64_t flg[TH];                 // per row: local roots of edge-touching components
+    uint16_t bbase[TH / 2];           // first node of every band
+};
+
+// Kernel 1 body for tile t of image v, binary labeling.  Writes the tile's
+// row masks, edge-root masks, band interval ends and band bases, one record
+// per node (the tile-local pixel of its root), the edge masks and the roots
+// of the edge cells, and seeds those roots in the forest.  Ends after a
+// workgroup barrier.
+template <int TH, int NW, bool CONN8>
+__device__ __forceinline__ void k1_tile_bands(const ImgView &v, uint32_t t, K1BandLds<TH> &sh) {
+    constexpr int RPW = TH / NW;
+    static_assert(RPW % 2 == 0, "a wavefront owns whole bands");
+    constexpr int BPW = RPW / 2;
+    constexpr int NB = TH / 2;
+    constexpr int NT = NW * 64;
+    constexpr int CH = TH * 4;               // 16-byte chunks per tile
+    constexpr int LPT = (CH + NT - 1) / NT;  // chunks per thread
+    uint32_t *par = sh.par;
+    uint64_t *msk = sh.msk;
+    uint64_t *flg = sh.flg;
+    const int tid = (int)threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+    const uint32_t TX = (uint32_t)v.tilesX;
+    const int tx = (int)(t % TX), ty = (int)(t / TX);
+    const bool hasUp = ty > 0, hasDown = ty + 1 < v.tilesY;
+    const bool hasLeft = tx > 0, hasRight = tx + 1 < v.tilesX;
+
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+        const int c = tid + i * NT;
+        if (c < CH) ((uint16_t *)msk)[c] = (uint16_t)nonzero_bytes16(load_chunk(v, tx, ty, TH, c >> 2, c & 3));
+    }
+    if (tid < TH) flg[tid] = 0ull;
+    __syncthreads();
+    // every band's intervals, one band per lane: nodes are numbered densely
+    // (an exclusive scan of the bands' interval counts)
+    uint32_t bbv, nodes;
+    {
+        const uint64_t bt = lane < NB ? msk[2 * lane] : 0ull, bb = lane < NB ? msk[2 * lane + 1] : 0ull;
+        const uint64_t s = band_starts<CONN8>(bt, bb);
+        bbv = wave_exclusive_scan((uint32_t)__popcll(s), &nodes);
+        if (tid < NB) {
+            sh.ends[tid] = band_ends(bt | bb, s);
+            sh.bbase[tid] = (uint16_t)bbv;
+        }
+    }
+    __syncthreads();
+    sweep_bands<BPW, CONN8>(par, msk, sh.ends, wave, lane, bbv);
+    if (NW > 1) {
+        __syncthreads();
+        if (wave > 0) {
+            const int k = wave * BPW;
+            merge_band_seam<CONN8>(par, msk, sh.ends, k, (uint32_t)__builtin_amdgcn_readlane((int)bbv, k),
+                                   (uint32_t)__builtin_amdgcn_readlane((int)bbv, k - 1));
+        }
+    }
+    __syncthreads();
+
+    // node-parallel finish: every node finds its root (read-only walk) and
+    // its owner alone stores it, so par[n] is the root's key afterwards; the
+    // node's record (the root's tile-local pixel) goes out
+    uint16_t *sl = v.slots + (size_t)t * TH * kSlotsPerRow;
+    for (uint32_t n = (uint32_t)tid; n < nodes; n += NT) {
+        const uint32_t e = lds_ld(&par[n]);
+        const uint32_t root = key_root(par, e);
+        if (root != e) lds_st(&par[n], root);
+        sl[n] = (uint16_t)(root >> kNodeBits);
+    }
+    __syncthreads();
+    uint64_t *rw = v.rowmask + (size_t)t * rowmask_words(TH);
+    if (tid < TH) rw[tid] = msk[tid];
+    if (tid < NB) {
+        rw[rowmask_ends(TH) + tid] = sh.ends[tid];
+        ((uint16_t *)(rw + rowmask_bases(TH)))[tid] = sh.bbase[tid];
+    }
+    // edge masks and edge-cell roots for the boundary analysis; every such
+    // root is seeded in the forest (lanes of one component store the same
+    // word) and marked in the edge-root masks
+    if (wave == 0) {
+        uint64_t *mk = v.masks + (size_t)t * 4;
+        uint32_t *rt = v.roots + (size_t)t * roots_per_tile(TH);
+        const uint64_t mTop = uniform64(msk[0]), mBot = uniform64(msk[TH - 1]);
+        auto root_g = [&](uint32_t n) {
+            const uint32_t pos = lds_ld(&par[n]) >> kNodeBits;
+            atomicOr((unsigned long long *)&flg[pos >> 6], 1ull << (pos & 63u));
+            return global_index(v, tx, ty, TH, pos);
+        };
+        auto put = [&](uint32_t *dst, uint32_t g) {
+            *dst = g;
+            v.labels[g] = g + 1u;
+        };
+        // first node of the last band, read while every lane is active (a
+        // lane that is off inside the branch below may not hold it)
+        const uint32_t bbLast = (uint32_t)__builtin_amdgcn_readlane((int)bbv, NB - 1);
+        if (hasUp && lane_in(mTop)) put(&rt[roots_top(TH) + lane], root_g(bits_below(uniform64(sh.ends[0]))));
+        if (hasDown && lane_in(mBot))
+            put(&rt[roots_bottom(TH) + lane], root_g(bbLast + bits_below(uniform64(sh.ends[NB - 1]))));
+        // per row (lane = row): the band's first / last interval holds the
+        // row's cell in the left / right column
+        const uint64_t mr = lane < TH ? msk[lane] : 0ull;
+        const bool lb = (mr & 1ull) != 0, rb = (mr >> 63) != 0;
+        const uint32_t bFirst = lane < TH ? (uint32_t)sh.bbase[lane >> 1] : 0u;
+        const uint32_t nInt = lane < TH ? (uint32_t)__popcll(sh.ends[lane >> 1]) : 0u;
+        const uint64_t mLeft = __ballot(lb), mRight = __ballot(rb);
+        if (hasLeft && lb) put(&rt[roots_left(TH) + lane], root_g(bFirst));
+        if (hasRight && rb) put(&rt[roots_right(TH) + lane], root_g(bFirst + nInt - 1u));
+        if (lane == 0) {
+            mk[kMaskTop] = mTop;
+            mk[kMaskBottom] = mBot;
+            mk[kMaskLeft] = mLeft;
+            mk[kMaskRight] = mRight;
+        }
+        // only this wavefront marks edge roots: once its own LDS operations
+        // have completed, the masks are whole
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (lane < TH) rw[TH + lane] = flg[lane];
+    }
+    __syncthreads();  // LDS may be reused for another tile
+}
+
 // ------------------------------------------------------ boundary analysis
 
 // One wavefront per tile: the tile's top edge against the tile above (64
@@ -359,30 +487,47 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, const uint
     // first record of this wave's rows (lane k: row wave*RPW + k): binary
     // records are numbered densely by the local merge, which stored every
     // row's first record; equal-value records have 64 slots per row
+    // binary records are numbered by two-row band (both rows of a band
+    // read the band's interval ends; a wavefront owns whole bands)
+    static_assert(EQ || RPW % 2 == 0, "a wavefront owns whole bands");
+    constexpr int BPW = EQ ? 1 : RPW / 2;
     uint32_t rbv;
     if (EQ) {
         rbv = (uint32_t)((wave * RPW + lane) * SPR);
     } else {
-        const uint16_t *rbg = (const uint16_t *)(rw + 2 * TH);
-        rbv = lane < RPW ? (uint32_t)rbg[wave * RPW + lane] : 0u;
+        const uint16_t *rbg = (const uint16_t *)(rw + rowmask_bases(TH));
+        rbv = lane < BPW ? (uint32_t)rbg[wave * BPW + lane] : 0u;
     }
-    uint64_t m[RPW], f[RPW];
+    uint64_t m[RPW], f[RPW], be[BPW];
     uint32_t rec[RPW];
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
         m[k] = uniform64(rm[k]);
         f[k] = uniform64(rm[TH + k]);
     }
+    if (!EQ) {
+#pragma unroll
+        for (int k = 0; k < BPW; ++k) be[k] = uniform64(rw[rowmask_ends(TH) + wave * BPW + k]);
+    }
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
-        // run of this lane (rank among the row's run starts at or below it;
-        // background lanes read some slot of the row and discard it)
+        // this lane's node (background lanes read some record of the tile
+        // and discard it): equal-value, the rank among the row's run
+        // starts at or below it; binary, the band's intervals ending before it
+        uint32_t node;
+        if (EQ) {
+            const uint64_t S = m[k];
+            const uint32_t below = bits_below(S) + (lane_in(S) ? 1u : 0u);
+            node = (uint32_t)__builtin_amdgcn_readlane((int)rbv, k) + (below ? below - 1u : 0u);
+        } else {
+            // lanes right of the band's last interval take that interval
+            const uint64_t E = be[k / 2];
+            const uint32_t below = bits_below(E), last = (uint32_t)__popcll(E);
+            node = (uint32_t)__builtin_amdgcn_readlane((int)rbv, k / 2) +
+                   (below < last ? below : (last ? last - 1u : 0u));
+        }
         const uint64_t d = EQ ? (k < rows_in ? cols : 0ull) : m[k];
-        const uint64_t S = EQ ? m[k] : run_starts(m[k]);
-        const uint32_t below = bits_below(S) + (lane_in(S) ? 1u : 0u);
-        const uint32_t rank = below ? below - 1u : 0u;
-        const uint32_t rb = (uint32_t)__builtin_amdgcn_readlane((int)rbv, k);
-        const uint32_t r = sl[rb + rank];
+        const uint32_t r = sl[node];
         rec[k] = lane_in(d) ? r : kNone;
     }
     // this wave's flagged roots, listed in row order
@@ -429,8 +574,14 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, const uint
 
 template <int TH, int NW, bool CONN8, bool EQ>
 __global__ void __launch_bounds__(NW * 64) k1_local_merge(ImgView v) {
-    __shared__ K1Lds<TH, EQ> sh;
-    k1_tile<TH, NW, CONN8, EQ>(v, xcd_remap(blockIdx.x, gridDim.x), sh);
+    const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
+    if constexpr (EQ) {
+        __shared__ K1Lds<TH, true> sh;
+        k1_tile<TH, NW, CONN8, true>(v, t, sh);
+    } else {
+        __shared__ K1BandLds<TH> sh;
+        k1_tile_bands<TH, NW, CONN8>(v, t, sh);
+    }
 }
 
 template <int TH, bool CONN8, bool EQ>
@@ -481,13 +632,13 @@ __device__ __forceinline__ ImgView batch_view(const BatchImage &b, const BatchWs
 // sizes the grids for every call.
 template <int TH, int NW, bool CONN8>
 __global__ void __launch_bounds__(NW * 64) k1_batch(BatchArgs a) {
-    __shared__ K1Lds<TH, false> sh;
+    __shared__ K1BandLds<TH> sh;
     const uint32_t g = xcd_remap(blockIdx.x, gridDim.x);
     if (g >= a.tiles) return;  // workgroup-uniform
     const uint32_t i = batch_image_of(a, g);
     if (threadIdx.x == 0) a.w.tile_img[g] = i;
     const BatchImage &d = a.descs[i];
-    k1_tile<TH, NW, CONN8, false>(batch_view<TH>(d, a.w), g - d.tile_base, sh);
+    k1_tile_bands<TH, NW, CONN8>(batch_view<TH>(d, a.w), g - d.tile_base, sh);
 }
 
 template <int TH, bool CONN8>
@@ -548,7 +699,7 @@ static void batch_kernels_t(BatchKernels *k) {
 
 bool config_supported(int th, int nw) {
     switch (th) {
-        case 16: return nw == 1 || nw == 2 || nw == 4 || nw == 8 || nw == 16;
+        case 16: return nw == 1 || nw == 2 || nw == 4 || nw == 8;
         case 32: return nw == 1 || nw == 2 || nw == 4 || nw == 8 || nw == 16;
         case 64: return nw == 1 || nw == 2 || nw == 4 || nw == 8 || nw == 16;
         default: return false;
@@ -556,7 +707,7 @@ bool config_supported(int th, int nw) {
 }
 
 #define CCL_FOR_EACH_CONFIG(X)                                                              \
-    X(16, 1) X(16, 2) X(16, 4) X(16, 8) X(16, 16) X(32, 1) X(32, 2) X(32, 4) X(32, 8) X(32, 16) \
+    X(16, 1) X(16, 2) X(16, 4) X(16, 8) X(32, 1) X(32, 2) X(32, 4) X(32, 8) X(32, 16) \
         X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(64, 16)
 
 // Tile configurations compiled for equal-value labeling.

@@ -105,13 +105,14 @@ def test_ex_validation():
 
 def test_workspace_size_formula():
     # per tile: 4 edge masks (8 B), 2*64 + 2*TH edge roots (4 B), 2*TH row
-    # masks (8 B: foreground, edge roots), TH two-byte row bases and 32
-    # two-byte run records per row; each part 256-byte aligned
+    # masks (8 B: foreground, edge roots), TH/2 band interval-end masks (8 B),
+    # TH/2 two-byte band bases and 32 two-byte records per row; each part
+    # 256-byte aligned
     for (H, W, th) in ((4096, 4096, 64), (100, 65, 16), (1, 1, 32)):
         tiles = (-(-W // 64)) * (-(-H // th))
         masks = -(-tiles * 32 // 256) * 256
         roots = -(-tiles * (128 + 2 * th) * 4 // 256) * 256
-        rowm = -(-tiles * (2 * th + th // 4) * 8 // 256) * 256
+        rowm = -(-tiles * (2 * th + th // 2 + th // 8) * 8 // 256) * 256
         slots = -(-tiles * th * 64 // 256) * 256
         assert binding.workspace_size(H, W, (th, 4 if th >= 4 else 1)) == masks + roots + rowm + slots
 
