@@ -60,8 +60,8 @@ typedef enum ccl_status {
 /* Tile configuration of the three kernels.  A tile is 64 pixels wide (one
  * 64-lane wavefront spans a tile row) and tile_h rows tall; each workgroup
  * runs `waves` wavefronts, each owning tile_h / waves consecutive rows.
- * Supported pairs: tile_h in {16, 32, 64}; waves in {1, 2, 4, 8, 16} with
- * tile_h / waves >= 2 (the binary local merge gives every wavefront whole
+ * Supported pairs: tile_h in {16, 32, 64, 128}; waves in {1, 2, 4, 8, 16} with
+ * tile_h / waves >= 2 and tile_h / waves <= 64 (the binary local merge gives every wavefront whole
  * two-row bands).  A zeroed struct or a NULL pointer selects the default. */
 typedef struct ccl_config {
     int32_t tile_h;

@@ -155,7 +155,7 @@ int ccl_ctx_create(ccl_ctx **out, const ccl_ctx_opts *opts) {
     }
 
     const size_t T = (size_t)c->max_tiles;
-    const size_t mb = align_up(T * 4 * sizeof(uint64_t), 256);
+    const size_t mb = align_up(T * (size_t)mask_words(c->th) * sizeof(uint64_t), 256);
     const size_t rb = align_up(T * (size_t)roots_per_tile(c->th) * sizeof(uint32_t), 256);
     const size_t rmb = align_up(T * (size_t)rowmask_words(c->th) * sizeof(uint64_t), 256);
     const size_t sb = align_up(T * (size_t)c->th * kSlotsPerRow * sizeof(uint16_t), 256);

@@ -1,15 +1,17 @@
 // Device-side building blocks of the three labeling phases (gfx950, wave64).
 //
 // Tile model.  A tile is 64 pixels wide -- one lane of a 64-wide wavefront
-// per column -- and TH rows tall (TH in {16, 32, 64}).  A workgroup of NW
+// per column -- and TH rows tall (TH in {16, 32, 64, 128}).  A workgroup of NW
 // wavefronts owns one tile at a time; wavefront w owns rows [w*RPW,
 // (w+1)*RPW) with RPW = TH / NW.  A tile row is a 64-bit foreground mask, so
 // the paper's row scan plus row-column unification (Sec. II-A-2) collapses
-// to: every pixel's provisional parent is the first pixel of its horizontal
-// run, found in O(1) from the mask.  Only run starts are union-find nodes.
-// The local UF (Sec. II-A-3) then merges each run with the runs it touches in
-// the row above through LDS atomicMin, always linking the larger index under
-// the smaller.
+// to mask arithmetic: binary labeling takes two rows at a time, and the
+// components of such a band are column intervals found from its two masks
+// (see sweep_bands); those intervals are the union-find nodes.  The local
+// UF (Sec. II-A-3) then merges each interval with the intervals of the band
+// above that it touches through LDS atomicMin, always linking the node with
+// the larger smallest pixel under the other.  Equal-value labeling keeps one
+// node per run of equal values in a row.
 //
 // Forest encoding in global memory.  labels[p] holds 1 + parent(p); a root r
 // holds r + 1 and background holds 0.  The final output is therefore itself a
@@ -17,17 +19,17 @@
 // while other tiles still walk the forest.
 //
 // Workspace per tile, written by the local merge:
-//   masks[4]        top-row, bottom-row, left-column, right-column foreground
-//                   masks (boundary analysis)
+//   masks[...]      top-row, bottom-row, left-column, right-column foreground
+//                   masks (boundary analysis; mask_words)
 //   roots[...]      global raster index of the tile-local root of every cell
 //                   on those four edges (boundary analysis)
 //   rowmask[...]    the 64-bit foreground mask of every tile row, then per
 //                   row the mask of the local root pixels whose component
-//                   touches a shared tile edge, then every row's first run
-//                   record (16 bits each) (link)
-//   slots[TH][32]   per row, one 16-bit record per run in left-to-right
-//                   order: the tile-local pixel index of the run's local
-//                   root (link)
+//                   touches a shared tile edge, then (binary labeling) every
+//                   two-row band's interval ends and first node (link)
+//   slots[...]      one 16-bit record per union-find node (binary: per band
+//                   interval; equal-value: per run, 64 slots per row): the
+//                   tile-local pixel of the node's local root (link)
 // Every root of an edge-touching component is also seeded in the forest,
 // labels[root] = root + 1, before the boundary analysis runs.
 #pragma once
@@ -40,7 +42,12 @@ namespace ccl {
 constexpr int kTileW = 64;               // tile width == wavefront width
 constexpr uint32_t kNone = 0xFFFFFFFFu;  // "no node"
 
-enum { kMaskTop = 0, kMaskBottom = 1, kMaskLeft = 2, kMaskRight = 3 };
+// Edge masks of a tile: the top and bottom rows (one word each), then the
+// left and the right column, one bit per row (one word per 64 rows each).
+enum { kMaskTop = 0, kMaskBottom = 1, kMaskLeft = 2 };
+__host__ __device__ constexpr int col_words(int th) { return (th + 63) / 64; }
+__host__ __device__ constexpr int mask_words(int th) { return 2 + 2 * col_words(th); }
+__host__ __device__ constexpr int mask_right(int th) { return kMaskLeft + col_words(th); }
 
 // Run records per tile row: a 64-pixel row has at most 32 foreground runs,
 // and at most 64 equal-value runs.
@@ -64,7 +71,7 @@ __host__ __device__ constexpr int roots_right(int th) { return 2 * kTileW + th; 
 struct ImgView {
     const uint8_t *img;
     uint32_t *labels;
-    uint64_t *masks;    // [tiles][4]
+    uint64_t *masks;    // [tiles][mask_words(TH)]
     uint32_t *roots;    // [tiles][roots_per_tile(TH)]
     uint64_t *rowmask;  // [tiles][rowmask_words(TH)]: row masks, edge-root masks, row bases
     uint16_t *slots;    // [tiles][TH][slots_per_row]
@@ -530,39 +537,6 @@ __device__ __forceinline__ void sweep_band(uint32_t *par, uint16_t *cr, const ui
     }
 }
 
-// Merge tile row r with the row ru above it (a band seam), any forest
-// state; each pair of touching runs is joined once.
-// `base` / `base_u`: first node of row r / ru.
-template <bool CONN8>
-__device__ __forceinline__ void merge_rows(uint32_t *par, const uint64_t *msk, int r, int ru,
-                                           uint32_t base, uint32_t base_u) {
-    auto join = [&](uint32_t a, uint32_t b) { lds_link(par, a, b); };
-    const uint64_t d = uniform64(msk[r]), u = uniform64(msk[ru]);
-    const uint64_t S = run_starts(d), Su = run_starts(u);
-    const bool isS = lane_in(S);
-    const uint32_t node = base + bits_below(S) - (isS ? 0u : 1u);
-    const uint32_t up = base_u;
-    const uint32_t bu = bits_below(Su);
-    const PairMasks p = pair_masks<CONN8>(d, u);
-    if (CONN8) {
-        // PL: upper run containing j-1 (rank = starts at or below j-1, minus 1);
-        // PM / PR: upper run starting at j / j+1 (rank = starts below j)
-        if (lane_in(p.pl)) join(node, up + bu - 1u);
-        else if (lane_in(p.pm)) join(node, up + bu);
-        if (lane_in(p.pr)) join(node, up + bu);
-    } else {
-        if (lane_in(p.pm)) join(node, up + bu - (lane_in(Su) ? 0u : 1u));
-    }
-}
-
-// Band seam of a multi-wavefront tile: the first row of band `wave` against
-// the last row of the band above.
-template <bool CONN8>
-__device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, int r, uint32_t rbv) {
-    merge_rows<CONN8>(par, msk, r, r - 1, (uint32_t)__builtin_amdgcn_readlane((int)rbv, r),
-                      (uint32_t)__builtin_amdgcn_readlane((int)rbv, r - 1));
-}
-
 // ------------------------------------------------- two-row band nodes
 //
 // The binary local merge takes the tile two rows at a time.  Inside such a
@@ -582,7 +556,7 @@ __device__ __forceinline__ void merge_seam(uint32_t *par, const uint64_t *msk, i
 // linking rule of Sec. II-A-3, with pixels as the order).  A root's entry is
 // its own key.
 
-constexpr uint32_t kNodeBits = 11;  // at most 2048 nodes per tile (64 intervals per band)
+constexpr uint32_t kNodeBits = 12;  // at most 4096 nodes per tile (64 intervals per band)
 constexpr uint32_t kNodeMask = (1u << kNodeBits) - 1u;
 
 // First column of every interval of the band (t above b).

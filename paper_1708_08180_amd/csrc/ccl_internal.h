@@ -53,7 +53,7 @@ inline WsLayout ws_layout(int H, int W, int th, bool equal = false) {
     const size_t tx = ((size_t)W + kTileW - 1) / kTileW;
     const size_t ty = ((size_t)H + th - 1) / th;
     l.tiles = tx * ty;
-    l.mask_bytes = align_up(l.tiles * 4 * sizeof(uint64_t), 256);
+    l.mask_bytes = align_up(l.tiles * (size_t)mask_words(th) * sizeof(uint64_t), 256);
     l.root_bytes = align_up(l.tiles * (size_t)roots_per_tile(th) * sizeof(uint32_t), 256);
     l.rowmask_bytes = align_up(l.tiles * (size_t)rowmask_words(th) * sizeof(uint64_t), 256);
     const size_t spr = equal ? (size_t)slots_per_row<true>() : (size_t)slots_per_row<false>();

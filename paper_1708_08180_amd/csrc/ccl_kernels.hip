@@ -28,27 +28,25 @@ namespace ccl {
 
 // ------------------------------------------------------------- local merge
 
-template <int TH, bool EQ>
-struct K1Lds {
-    static constexpr int SPR = slots_per_row<EQ>();
-    // every run's first column | row << 8 (equal-value: the column only; the
-    // row of node n is n / 64 there)
-    using CR = typename std::conditional<EQ, uint8_t, uint16_t>::type;
-    uint32_t par[TH * SPR];  // run-indexed parents
-    CR cr[TH * SPR];
-    uint64_t msk[TH];        // per row: foreground mask (binary) / run starts (equal-value)
-    uint64_t flg[TH];        // per row: local roots of edge-touching components
-    uint16_t rinfo[TH];      // equal-value: runs | 0x100: first run at column 0 | 0x200: last ends at 63
-    uint16_t rbase[TH];      // first node of every row (binary: dense numbering)
-    alignas(16) uint8_t pix[EQ ? TH * kTileW : 16];  // the tile's bytes (equal-value only)
+// Equal-value local merge (every value class labeled, Sec. II-A's
+// "same property" test): nodes are the runs of equal values of every row,
+// 64 slots per row, swept row by row (sweep_band_eq).
+template <int TH>
+struct K1EqLds {
+    static constexpr int SPR = slots_per_row<true>();
+    uint32_t par[TH * SPR];                // run-indexed parents
+    uint8_t col[TH * SPR];                 // every run's first column (node n lies in row n / 64)
+    uint64_t msk[TH];                      // per row: run starts
+    uint64_t flg[TH];                      // per row: local roots of edge-touching components
+    uint16_t rinfo[TH];                    // runs | 0x100: first run at column 0 | 0x200: last ends at 63
+    alignas(16) uint8_t pix[TH * kTileW];  // the tile's bytes
 };
 
-// Kernel 1 body for tile t of image v.  EQ selects equal-value labeling
-// (every value class) instead of binary foreground labeling.  Ends after a
-// workgroup barrier, so the caller may reuse the LDS for the next tile.
-template <int TH, int NW, bool CONN8, bool EQ>
-__device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, EQ> &sh) {
-    constexpr int SPR = slots_per_row<EQ>();
+// Kernel 1 body for tile t of image v, equal-value labeling.  Ends after a
+// workgroup barrier, so the caller may reuse the LDS for another tile.
+template <int TH, int NW, bool CONN8>
+__device__ __forceinline__ void k1_tile_eq(const ImgView &v, uint32_t t, K1EqLds<TH> &sh) {
+    constexpr int SPR = slots_per_row<true>();
     constexpr int RPW = TH / NW;
     constexpr int NT = NW * 64;
     constexpr int CH = TH * 4;                  // 16-byte chunks per tile
@@ -56,14 +54,10 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
     constexpr int NODES = TH * SPR;             // run-indexed nodes per tile
     constexpr int NPT = (NODES + NT - 1) / NT;  // nodes per thread
     uint32_t *par = sh.par;
-    typename K1Lds<TH, EQ>::CR *cr = sh.cr;
-    // tile row and first column of run node n
-    auto run_row = [&](uint32_t n) { return EQ ? n / (uint32_t)SPR : (uint32_t)cr[n] >> 8; };
-    auto run_col = [&](uint32_t n) { return (uint32_t)cr[n] & 0xFFu; };
+    uint8_t *col = sh.col;
     uint64_t *msk = sh.msk;
     uint64_t *flg = sh.flg;
     uint16_t *rinfo = sh.rinfo;
-    uint16_t *rbase = sh.rbase;
     const int tid = (int)threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     const uint32_t TX = (uint32_t)v.tilesX;
@@ -73,41 +67,17 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
     // columns / rows of the tile inside the image
     const int wlim = min(kTileW, v.W - tx * kTileW), hlim = min(TH, v.H - ty * TH);
 
-    // the tile's rows: row masks (binary) or the raw bytes (equal-value)
 #pragma unroll
     for (int i = 0; i < LPT; ++i) {
         const int c = tid + i * NT;
-        if (c < CH) {
-            const uint4 b = load_chunk(v, tx, ty, TH, c >> 2, c & 3);
-            if (EQ) ((uint4 *)sh.pix)[c] = b;
-            else ((uint16_t *)msk)[c] = (uint16_t)nonzero_bytes16(b);
-        }
+        if (c < CH) ((uint4 *)sh.pix)[c] = load_chunk(v, tx, ty, TH, c >> 2, c & 3);
     }
     if (tid < TH) flg[tid] = 0ull;
     __syncthreads();
-    // first node of every row, one row per lane: binary labeling numbers the
-    // runs densely (an exclusive scan of the rows' run counts, so the finish
-    // pass visits only real runs); equal-value labeling keeps 64 per row
-    uint32_t rbv, nodes;
-    if (EQ) {
-        rbv = (uint32_t)(lane * SPR);
-        nodes = (uint32_t)NODES;
-    } else {
-        const uint64_t dj = lane < TH ? msk[lane] : 0ull;
-        rbv = wave_exclusive_scan((uint32_t)__popcll(run_starts(dj)), &nodes);
-        if (tid < TH) rbase[tid] = (uint16_t)rbv;
-    }
-    if constexpr (EQ) {
-        sweep_band_eq<TH, RPW, CONN8>(par, cr, msk, rinfo, sh.pix, wave, lane, wlim, hlim);
-    } else {
-        sweep_band<TH, RPW, CONN8>(par, cr, msk, wave, lane, rbv);
-    }
+    sweep_band_eq<TH, RPW, CONN8>(par, col, msk, rinfo, sh.pix, wave, lane, wlim, hlim);
     if (NW > 1) {
         __syncthreads();
-        if (wave > 0) {
-            if (EQ) merge_seam_eq<CONN8>(par, msk, sh.pix, wave * RPW, lane, wlim, hlim);
-            else merge_seam<CONN8>(par, msk, wave * RPW, rbv);
-        }
+        if (wave > 0) merge_seam_eq<CONN8>(par, msk, sh.pix, wave * RPW, lane, wlim, hlim);
     }
     __syncthreads();
 
@@ -118,36 +88,29 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
         const int n = tid + i * NT;
-        if (n >= (int)nodes) break;
-        // equal-value numbering leaves unused slots at the end of each row
-        if (EQ && n % SPR >= (int)(rinfo[n / SPR] & 0x7Fu)) continue;
+        // the numbering leaves unused slots at the end of each row
+        if (n % SPR >= (int)(rinfo[n / SPR] & 0x7Fu)) continue;
         const uint32_t root = lds_root(par, (uint32_t)n);
         if (root != (uint32_t)n) lds_st(&par[n], root);
-        sl[n] = (uint16_t)(run_row(root) * kTileW + run_col(root));
+        sl[n] = (uint16_t)((root / SPR) * kTileW + col[root]);
     }
     __syncthreads();
-    if (tid < TH) {
-        uint64_t *rw = v.rowmask + (size_t)t * rowmask_words(TH);
-        rw[tid] = msk[tid];
-        if (!EQ) ((uint16_t *)(rw + 2 * TH))[tid] = rbase[tid];
-    }
+    if (tid < TH) v.rowmask[(size_t)t * rowmask_words(TH) + tid] = msk[tid];
     // edge masks and edge-cell roots for the boundary analysis; every such
     // root is seeded in the forest (lanes of one component store the same
     // word)
     if (wave == 0) {
-        uint64_t *mk = v.masks + (size_t)t * 4;
+        uint64_t *mk = v.masks + (size_t)t * mask_words(TH);
         uint32_t *rt = v.roots + (size_t)t * roots_per_tile(TH);
         // cells taking part in the top / bottom row, run starts of those rows
         const uint64_t cols = wlim == 64 ? ~0ull : ((1ull << wlim) - 1ull);
-        const uint64_t mTop = EQ ? cols : uniform64(msk[0]);
-        const uint64_t mBot = EQ ? (TH - 1 < hlim ? cols : 0ull) : uniform64(msk[TH - 1]);
-        const uint64_t sTop = EQ ? uniform64(msk[0]) : run_starts(mTop);
-        const uint64_t sBot = EQ ? uniform64(msk[TH - 1]) : run_starts(mBot);
+        const uint64_t mTop = cols, mBot = TH - 1 < hlim ? cols : 0ull;
+        const uint64_t sTop = uniform64(msk[0]), sBot = uniform64(msk[TH - 1]);
         // global index of the root pixel of run node n; the root is marked
         // in the edge-root masks (its component touches a shared edge)
         auto root_g = [&](uint32_t n) {
             const uint32_t root = lds_ld(&par[n]);
-            const uint32_t rr = run_row(root), rc = run_col(root);
+            const uint32_t rr = root / SPR, rc = col[root];
             atomicOr((unsigned long long *)&flg[rr], 1ull << rc);
             return global_index(v, tx, ty, TH, rr * kTileW + rc);
         };
@@ -155,31 +118,27 @@ __device__ __forceinline__ void k1_tile(const ImgView &v, uint32_t t, K1Lds<TH, 
             *dst = g;
             v.labels[g] = g + 1u;
         };
-        // first node of the bottom row, read while every lane is active (a
-        // lane that is off inside the branch below may not hold it)
-        const uint32_t rbBot = (uint32_t)__builtin_amdgcn_readlane((int)rbv, TH - 1);
         if (hasUp && lane_in(mTop)) {
             const uint32_t n = bits_below(sTop) - (lane_in(sTop) ? 0u : 1u);
             put(&rt[roots_top(TH) + lane], root_g(n));
         }
         if (hasDown && lane_in(mBot)) {
-            const uint32_t n = rbBot + bits_below(sBot) - (lane_in(sBot) ? 0u : 1u);
+            const uint32_t n = (uint32_t)((TH - 1) * SPR) + bits_below(sBot) - (lane_in(sBot) ? 0u : 1u);
             put(&rt[roots_bottom(TH) + lane], root_g(n));
         }
         // per row (lane = row): cells in the left / right column, last run
         const uint64_t mr = lane < TH ? msk[lane] : 0ull;
         const bool rowIn = lane < hlim;
-        const bool lb = EQ ? rowIn : (mr & 1ull) != 0;
-        const bool rb = EQ ? (rowIn && wlim == 64) : (mr >> 63) != 0;
-        const int lastRun = __popcll(EQ ? mr : run_starts(mr)) - 1;
+        const bool lb = rowIn, rb = rowIn && wlim == 64;
+        const uint32_t first = (uint32_t)(lane * SPR), lastRun = (uint32_t)__popcll(mr) - 1u;
         const uint64_t mLeft = __ballot(lb), mRight = __ballot(rb);
-        if (hasLeft && lb) put(&rt[roots_left(TH) + lane], root_g(rbv));
-        if (hasRight && rb) put(&rt[roots_right(TH) + lane], root_g(rbv + (uint32_t)lastRun));
+        if (hasLeft && lb) put(&rt[roots_left(TH) + lane], root_g(first));
+        if (hasRight && rb) put(&rt[roots_right(TH) + lane], root_g(first + lastRun));
         if (lane == 0) {
             mk[kMaskTop] = mTop;
             mk[kMaskBottom] = mBot;
             mk[kMaskLeft] = mLeft;
-            mk[kMaskRight] = mRight;
+            mk[mask_right(TH)] = mRight;
         }
         // only this wavefront marks edge roots: once its own LDS operations
         // have completed, the masks are whole
@@ -229,7 +188,7 @@ __device__ __forceinline__ void k1_tile_bands(const ImgView &v, uint32_t t, K1Ba
         const int c = tid + i * NT;
         if (c < CH) ((uint16_t *)msk)[c] = (uint16_t)nonzero_bytes16(load_chunk(v, tx, ty, TH, c >> 2, c & 3));
     }
-    if (tid < TH) flg[tid] = 0ull;
+    for (int r = tid; r < TH; r += NT) flg[r] = 0ull;
     __syncthreads();
     // every band's intervals, one band per lane: nodes are numbered densely
     // (an exclusive scan of the bands' interval counts)
@@ -267,7 +226,7 @@ __device__ __forceinline__ void k1_tile_bands(const ImgView &v, uint32_t t, K1Ba
     }
     __syncthreads();
     uint64_t *rw = v.rowmask + (size_t)t * rowmask_words(TH);
-    if (tid < TH) rw[tid] = msk[tid];
+    for (int r = tid; r < TH; r += NT) rw[r] = msk[r];
     if (tid < NB) {
         rw[rowmask_ends(TH) + tid] = sh.ends[tid];
         ((uint16_t *)(rw + rowmask_bases(TH)))[tid] = sh.bbase[tid];
@@ -276,7 +235,7 @@ __device__ __forceinline__ void k1_tile_bands(const ImgView &v, uint32_t t, K1Ba
     // root is seeded in the forest (lanes of one component store the same
     // word) and marked in the edge-root masks
     if (wave == 0) {
-        uint64_t *mk = v.masks + (size_t)t * 4;
+        uint64_t *mk = v.masks + (size_t)t * mask_words(TH);
         uint32_t *rt = v.roots + (size_t)t * roots_per_tile(TH);
         const uint64_t mTop = uniform64(msk[0]), mBot = uniform64(msk[TH - 1]);
         auto root_g = [&](uint32_t n) {
@@ -294,26 +253,32 @@ __device__ __forceinline__ void k1_tile_bands(const ImgView &v, uint32_t t, K1Ba
         if (hasUp && lane_in(mTop)) put(&rt[roots_top(TH) + lane], root_g(bits_below(uniform64(sh.ends[0]))));
         if (hasDown && lane_in(mBot))
             put(&rt[roots_bottom(TH) + lane], root_g(bbLast + bits_below(uniform64(sh.ends[NB - 1]))));
-        // per row (lane = row): the band's first / last interval holds the
-        // row's cell in the left / right column
-        const uint64_t mr = lane < TH ? msk[lane] : 0ull;
-        const bool lb = (mr & 1ull) != 0, rb = (mr >> 63) != 0;
-        const uint32_t bFirst = lane < TH ? (uint32_t)sh.bbase[lane >> 1] : 0u;
-        const uint32_t nInt = lane < TH ? (uint32_t)__popcll(sh.ends[lane >> 1]) : 0u;
-        const uint64_t mLeft = __ballot(lb), mRight = __ballot(rb);
-        if (hasLeft && lb) put(&rt[roots_left(TH) + lane], root_g(bFirst));
-        if (hasRight && rb) put(&rt[roots_right(TH) + lane], root_g(bFirst + nInt - 1u));
+        // per row (lane = row, 64 rows at a time): the band's first / last
+        // interval holds the row's cell in the left / right column
+#pragma unroll
+        for (int h = 0; h < col_words(TH); ++h) {
+            const int r = 64 * h + lane;
+            const uint64_t mr = r < TH ? msk[r] : 0ull;
+            const bool lb = (mr & 1ull) != 0, rb = (mr >> 63) != 0;
+            const uint32_t bFirst = r < TH ? (uint32_t)sh.bbase[r >> 1] : 0u;
+            const uint32_t nInt = r < TH ? (uint32_t)__popcll(sh.ends[r >> 1]) : 0u;
+            const uint64_t mLeft = __ballot(lb), mRight = __ballot(rb);
+            if (hasLeft && lb) put(&rt[roots_left(TH) + r], root_g(bFirst));
+            if (hasRight && rb) put(&rt[roots_right(TH) + r], root_g(bFirst + nInt - 1u));
+            if (lane == 0) {
+                mk[kMaskLeft + h] = mLeft;
+                mk[mask_right(TH) + h] = mRight;
+            }
+        }
         if (lane == 0) {
             mk[kMaskTop] = mTop;
             mk[kMaskBottom] = mBot;
-            mk[kMaskLeft] = mLeft;
-            mk[kMaskRight] = mRight;
         }
         // only this wavefront marks edge roots: once its own LDS operations
         // have completed, the masks are whole
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        if (lane < TH) rw[TH + lane] = flg[lane];
+        for (int r = lane; r < TH; r += 64) rw[TH + r] = flg[r];
     }
     __syncthreads();  // LDS may be reused for another tile
 }
@@ -331,41 +296,48 @@ __device__ __forceinline__ void k1_tile_bands(const ImgView &v, uint32_t t, K1Ba
 template <int TH, bool CONN8>
 __device__ __forceinline__ void k2_tile(const ImgView &v, uint32_t t) {
     constexpr int RT = roots_per_tile(TH);
+    constexpr int MW = mask_words(TH);
+    constexpr int LH = col_words(TH);  // left-edge cells per lane
     const int lane = lane_id();
     const uint32_t TX = (uint32_t)v.tilesX;
     const uint32_t tx = t % TX, ty = t / TX;
     const bool hasT = ty > 0, hasL = tx > 0, hasR = tx + 1u < TX;
     const uint64_t *mk = v.masks;
     const uint32_t *rts = v.roots;
-    uint64_t dT = 0, uT = 0, xl = 0, xr = 0, dL = 0, uL = 0;
-    uint32_t aT = kNone, rT = kNone, eTL = kNone, eTR = kNone, aL = kNone, rL = kNone;
+    uint64_t dT = 0, uT = 0, xl = 0, xr = 0, dL[LH], uL[LH];
+    uint32_t aT = kNone, rT = kNone, eTL = kNone, eTR = kNone, aL[LH], rL[LH];
     if (hasT) {
         const uint32_t tu = t - TX;
-        dT = mk[(size_t)t * 4 + kMaskTop];
-        uT = mk[(size_t)tu * 4 + kMaskBottom];
+        dT = mk[(size_t)t * MW + kMaskTop];
+        uT = mk[(size_t)tu * MW + kMaskBottom];
         if (hasL) {
-            xl = mk[(size_t)(tu - 1u) * 4 + kMaskBottom] >> 63;
+            xl = mk[(size_t)(tu - 1u) * MW + kMaskBottom] >> 63;
             eTL = rts[(size_t)(tu - 1u) * RT + roots_bottom(TH) + 63];
         }
         if (hasR) {
-            xr = (mk[(size_t)(tu + 1u) * 4 + kMaskBottom] & 1ull) << 63;
+            xr = (mk[(size_t)(tu + 1u) * MW + kMaskBottom] & 1ull) << 63;
             eTR = rts[(size_t)(tu + 1u) * RT + roots_bottom(TH)];
         }
         aT = rts[(size_t)t * RT + roots_top(TH) + lane];
         rT = rts[(size_t)tu * RT + roots_bottom(TH) + lane];
     }
-    if (hasL) {
-        dL = mk[(size_t)t * 4 + kMaskLeft];
-        uL = mk[(size_t)(t - 1u) * 4 + kMaskRight];
-        if (lane < TH) {
-            aL = rts[(size_t)t * RT + roots_left(TH) + lane];
-            rL = rts[(size_t)(t - 1u) * RT + roots_right(TH) + lane];
+#pragma unroll
+    for (int h = 0; h < LH; ++h) {
+        const int r = 64 * h + lane;
+        dL[h] = uL[h] = 0ull;
+        aL[h] = rL[h] = kNone;
+        if (hasL) {
+            dL[h] = mk[(size_t)t * MW + kMaskLeft + h];
+            uL[h] = mk[(size_t)(t - 1u) * MW + mask_right(TH) + h];
+            if (r < TH) {
+                aL[h] = rts[(size_t)t * RT + roots_left(TH) + r];
+                rL[h] = rts[(size_t)(t - 1u) * RT + roots_right(TH) + r];
+            }
         }
     }
     // roots of the cells above-left / above-right (left edge: above / below)
     const uint32_t bTl = from_left(rT, eTL), bTr = from_right(rT, eTR);
-    const uint32_t bLl = from_left(rL, kNone), bLr = from_right(rL, kNone);
-    uint32_t A[4], B[4];
+    uint32_t A[2 + 2 * LH], B[2 + 2 * LH];
     {
         const PairMasks p = pair_masks<CONN8>(dT, uT, xl, xr);
         // at lane 0 the above-left cell lies in the tile to the left, so
@@ -374,13 +346,22 @@ __device__ __forceinline__ void k2_tile(const ImgView &v, uint32_t t) {
         B[1] = lane_in(p.pr) ? bTr : (lane_in(p.pl & p.pm) ? rT : kNone);
         A[0] = A[1] = aT;
     }
-    {
-        const PairMasks p = pair_masks<CONN8>(dL, uL);
-        B[2] = lane_in(p.pl) ? bLl : (lane_in(p.pm) ? rL : kNone);
-        B[3] = lane_in(p.pr) ? bLr : kNone;
-        A[2] = A[3] = aL;
+    // the left edge as lines of 64 rows; the rows next to a chunk boundary
+    // come from the neighbouring chunk, the tile's own first and last rows
+    // have none (their corner pairs belong to the top edges)
+#pragma unroll
+    for (int h = 0; h < LH; ++h) {
+        const uint64_t cl = h > 0 ? uL[h - 1] >> 63 : 0ull;
+        const uint64_t cr = h + 1 < LH ? (uL[h + 1] & 1ull) << 63 : 0ull;
+        const uint32_t el = h > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)rL[h - 1], 63) : kNone;
+        const uint32_t er = h + 1 < LH ? (uint32_t)__builtin_amdgcn_readlane((int)rL[h + 1], 0) : kNone;
+        const uint32_t bLl = from_left(rL[h], el), bLr = from_right(rL[h], er);
+        const PairMasks p = pair_masks<CONN8>(dL[h], uL[h], cl, cr);
+        B[2 + 2 * h] = lane_in(p.pl) ? bLl : (lane_in(p.pm) ? rL[h] : kNone);
+        B[3 + 2 * h] = lane_in(p.pr) ? bLr : (lane_in(p.pl & p.pm) ? rL[h] : kNone);
+        A[2 + 2 * h] = A[3 + 2 * h] = aL[h];
     }
-    union_requests<4>(A, B, [&](uint32_t a, uint32_t b) { g_union(v.labels, v.n, a, b); });
+    union_requests<2 + 2 * LH>(A, B, [&](uint32_t a, uint32_t b) { g_union(v.labels, v.n, a, b); });
 }
 
 // Equal-value boundary analysis for tile t: like k2_tile, but a pair of
@@ -459,9 +440,7 @@ __device__ __forceinline__ void k2_tile_eq(const ImgView &v, uint32_t t) {
 // after a workgroup barrier.
 //
 // A flagged root is the root of some edge cell, so a tile has at most
-// 2 * 64 + 2 * TH <= kFlagCap of them; `flist` holds kFlagCap entries per
-// wavefront.
-constexpr int kFlagCap = 256;
+// roots_per_tile(TH) of them; `flist` holds that many entries per wavefront.
 
 // `rw` / `sl`: the tile's row data and run records in the workspace (they
 // depend on the tile only, so their loads need not wait for the image's
@@ -469,7 +448,7 @@ constexpr int kFlagCap = 256;
 template <int TH, int NW, bool EQ>
 __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, const uint64_t *rw,
                                         const uint16_t *sl, uint32_t *fin, uint16_t *flist) {
-    static_assert(2 * kTileW + 2 * TH <= kFlagCap, "flagged-root list too small");
+    constexpr int kFlagCap = roots_per_tile(TH);
     constexpr int SPR = slots_per_row<EQ>();
     constexpr int RPW = TH / NW;
     const uint32_t TX = (uint32_t)v.tilesX;
@@ -484,11 +463,10 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, const uint
     const int wlim = min(kTileW, v.W - (int)tx * kTileW);
     const uint64_t cols = wlim == 64 ? ~0ull : ((1ull << wlim) - 1ull);
     const int rows_in = v.H - (int)ty * TH - wave * RPW;
-    // first record of this wave's rows (lane k: row wave*RPW + k): binary
-    // records are numbered densely by the local merge, which stored every
-    // row's first record; equal-value records have 64 slots per row
-    // binary records are numbered by two-row band (both rows of a band
-    // read the band's interval ends; a wavefront owns whole bands)
+    // first record of this wave's rows or bands (lane k: row or band k of
+    // the wave): equal-value records have 64 slots per row; binary records
+    // are numbered densely by two-row band, and the local merge stored every
+    // band's first record (a wavefront owns whole bands)
     static_assert(EQ || RPW % 2 == 0, "a wavefront owns whole bands");
     constexpr int BPW = EQ ? 1 : RPW / 2;
     uint32_t rbv;
@@ -499,7 +477,10 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, const uint
         rbv = lane < BPW ? (uint32_t)rbg[wave * BPW + lane] : 0u;
     }
     uint64_t m[RPW], f[RPW], be[BPW];
-    uint32_t rec[RPW];
+    // records: one per row (equal-value) or one per band, which both rows
+    // of the band share (binary)
+    constexpr int NR = EQ ? RPW : BPW;
+    uint32_t rec[NR];
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
         m[k] = uniform64(rm[k]);
@@ -510,25 +491,26 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, const uint
         for (int k = 0; k < BPW; ++k) be[k] = uniform64(rw[rowmask_ends(TH) + wave * BPW + k]);
     }
 #pragma unroll
-    for (int k = 0; k < RPW; ++k) {
+    for (int i = 0; i < NR; ++i) {
         // this lane's node (background lanes read some record of the tile
         // and discard it): equal-value, the rank among the row's run
-        // starts at or below it; binary, the band's intervals ending before it
+        // starts at or below it; binary, the band's intervals ending before
+        // it (lanes right of the band's last interval take that interval)
         uint32_t node;
+        uint64_t d;
         if (EQ) {
-            const uint64_t S = m[k];
+            const uint64_t S = m[i];
             const uint32_t below = bits_below(S) + (lane_in(S) ? 1u : 0u);
-            node = (uint32_t)__builtin_amdgcn_readlane((int)rbv, k) + (below ? below - 1u : 0u);
+            node = (uint32_t)__builtin_amdgcn_readlane((int)rbv, i) + (below ? below - 1u : 0u);
+            d = i < rows_in ? cols : 0ull;
         } else {
-            // lanes right of the band's last interval take that interval
-            const uint64_t E = be[k / 2];
+            const uint64_t E = be[i];
             const uint32_t below = bits_below(E), last = (uint32_t)__popcll(E);
-            node = (uint32_t)__builtin_amdgcn_readlane((int)rbv, k / 2) +
-                   (below < last ? below : (last ? last - 1u : 0u));
+            node = (uint32_t)__builtin_amdgcn_readlane((int)rbv, i) + (below < last ? below : (last ? last - 1u : 0u));
+            d = m[2 * i] | m[2 * i + 1];
         }
-        const uint64_t d = EQ ? (k < rows_in ? cols : 0ull) : m[k];
         const uint32_t r = sl[node];
-        rec[k] = lane_in(d) ? r : kNone;
+        rec[i] = lane_in(d) ? r : kNone;
     }
     // this wave's flagged roots, listed in row order
     uint16_t *fl = flist + wave * kFlagCap;
@@ -545,7 +527,7 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, const uint
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
         const uint32_t l = (uint32_t)((wave * RPW + k) * kTileW + lane);
-        if (rec[k] == l && !lane_in(f[k])) fin[l] = origin + (l >> 6) * W + (l & 63u);
+        if (rec[EQ ? k : k / 2] == l && !lane_in(f[k])) fin[l] = origin + (l >> 6) * W + (l & 63u);
     }
     // the list is read back by other lanes of this wavefront
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
@@ -559,13 +541,20 @@ __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, const uint
     const uint32_t y0 = ty * (uint32_t)TH + (uint32_t)(wave * RPW);
     uint32_t *out = v.labels + origin + (uint32_t)(wave * RPW) * W + (uint32_t)lane;
     const bool full = (tx + 1u) * kTileW <= W && y0 + RPW <= (uint32_t)v.H;
+    // streaming stores: the output is not read again here, and keeping it
+    // out of the L2 leaves the records and the forest cached for the tiles
+    // still to run (a stale cached label is an ancestor)
 #pragma unroll
-    for (int k = 0; k < RPW; ++k) {
-        const uint32_t val = rec[k] != kNone ? fin[rec[k] & (TH * kTileW - 1)] + 1u : 0u;
-        // streaming stores: the output is not read again here, and keeping
-        // it out of the L2 leaves the run records and the forest cached
-        // for the tiles still to run (a stale cached label is an ancestor)
-        if (full || (x < W && y0 + k < (uint32_t)v.H)) __builtin_nontemporal_store(val, &out[(size_t)k * W]);
+    for (int i = 0; i < NR; ++i) {
+        const uint32_t val = rec[i] != kNone ? fin[rec[i] & (TH * kTileW - 1)] + 1u : 0u;
+        if (EQ) {
+            if (full || (x < W && y0 + i < (uint32_t)v.H)) __builtin_nontemporal_store(val, &out[(size_t)i * W]);
+        } else {
+            const int k = 2 * i;
+            const uint32_t v0 = lane_in(m[k]) ? val : 0u, v1 = lane_in(m[k + 1]) ? val : 0u;
+            if (full || (x < W && y0 + k < (uint32_t)v.H)) __builtin_nontemporal_store(v0, &out[(size_t)k * W]);
+            if (full || (x < W && y0 + k + 1 < (uint32_t)v.H)) __builtin_nontemporal_store(v1, &out[(size_t)(k + 1) * W]);
+        }
     }
     __syncthreads();
 }
@@ -576,8 +565,8 @@ template <int TH, int NW, bool CONN8, bool EQ>
 __global__ void __launch_bounds__(NW * 64) k1_local_merge(ImgView v) {
     const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
     if constexpr (EQ) {
-        __shared__ K1Lds<TH, true> sh;
-        k1_tile<TH, NW, CONN8, true>(v, t, sh);
+        __shared__ K1EqLds<TH> sh;
+        k1_tile_eq<TH, NW, CONN8>(v, t, sh);
     } else {
         __shared__ K1BandLds<TH> sh;
         k1_tile_bands<TH, NW, CONN8>(v, t, sh);
@@ -598,7 +587,7 @@ __global__ void __launch_bounds__(256) k2_boundary(ImgView v, uint32_t tiles) {
 template <int TH, int NW, bool EQ>
 __global__ void __launch_bounds__(NW * 64) k3_link(ImgView v) {
     __shared__ uint32_t fin[TH * kTileW];
-    __shared__ uint16_t flist[NW * kFlagCap];
+    __shared__ uint16_t flist[NW * roots_per_tile(TH)];
     constexpr int SPR = slots_per_row<EQ>();
     const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
     k3_tile<TH, NW, EQ>(v, t, v.rowmask + (size_t)t * rowmask_words(TH), v.slots + (size_t)t * TH * SPR,
@@ -612,7 +601,7 @@ __device__ __forceinline__ ImgView batch_view(const BatchImage &b, const BatchWs
     ImgView v;
     v.img = b.img;
     v.labels = b.labels;
-    v.masks = w.masks + (size_t)b.tile_base * 4;
+    v.masks = w.masks + (size_t)b.tile_base * mask_words(TH);
     v.roots = w.roots + (size_t)b.tile_base * roots_per_tile(TH);
     v.rowmask = w.rowmask + (size_t)b.tile_base * rowmask_words(TH);
     v.slots = w.slots + (size_t)b.tile_base * TH * kSlotsPerRow;
@@ -653,7 +642,7 @@ __global__ void __launch_bounds__(256) k2_batch(BatchArgs a) {
 template <int TH, int NW>
 __global__ void __launch_bounds__(NW * 64) k3_batch(BatchArgs a) {
     __shared__ uint32_t fin[TH * kTileW];
-    __shared__ uint16_t flist[NW * kFlagCap];
+    __shared__ uint16_t flist[NW * roots_per_tile(TH)];
     const uint32_t g = xcd_remap(blockIdx.x, gridDim.x);
     if (g >= a.tiles) return;  // workgroup-uniform
     const BatchImage &d = a.descs[a.w.tile_img[g]];
@@ -702,13 +691,14 @@ bool config_supported(int th, int nw) {
         case 16: return nw == 1 || nw == 2 || nw == 4 || nw == 8;
         case 32: return nw == 1 || nw == 2 || nw == 4 || nw == 8 || nw == 16;
         case 64: return nw == 1 || nw == 2 || nw == 4 || nw == 8 || nw == 16;
+        case 128: return nw == 2 || nw == 4 || nw == 8 || nw == 16;
         default: return false;
     }
 }
 
 #define CCL_FOR_EACH_CONFIG(X)                                                              \
     X(16, 1) X(16, 2) X(16, 4) X(16, 8) X(32, 1) X(32, 2) X(32, 4) X(32, 8) X(32, 16) \
-        X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(64, 16)
+        X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(64, 16) X(128, 2) X(128, 4) X(128, 8) X(128, 16)
 
 // Tile configurations compiled for equal-value labeling.
 #define CCL_FOR_EACH_EQ_CONFIG(X) X(16, 4) X(32, 2) X(32, 8) X(64, 4) X(64, 8)

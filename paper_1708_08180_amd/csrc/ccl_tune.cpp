@@ -87,7 +87,7 @@ int ccl_autotune(const uint8_t *img, int32_t H, int32_t W, int64_t pitch, int32_
         if (a) (void)hipEventDestroy(a);
         return fail_hip(e);
     }
-    static const int kTh[] = {16, 32, 64};
+    static const int kTh[] = {16, 32, 64, 128};
     static const int kNw[] = {1, 2, 4, 8, 16};
     float bestv = 1e30f;
     ccl_config bc = {0, 0};

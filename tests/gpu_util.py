@@ -7,7 +7,7 @@ import sys
 import numpy as np
 
 # every compiled tile configuration (tile_h, waves)
-CONFIGS = [(64, 4), (64, 8), (64, 16), (64, 1), (64, 2), (32, 1), (32, 2), (32, 4), (32, 8),
+CONFIGS = [(64, 4), (64, 8), (64, 16), (64, 1), (64, 2), (128, 8), (128, 4), (128, 16), (128, 2), (32, 1), (32, 2), (32, 4), (32, 8),
            (32, 16), (16, 1), (16, 2), (16, 4), (16, 8)]
 
 
