@@ -420,17 +420,18 @@ __device__ __forceinline__ uint64_t run_starts(uint64_t d) { return d & ~(d << 1
 __device__ __forceinline__ uint64_t run_ends(uint64_t d) { return d & ~(d >> 1); }
 
 // Exclusive prefix sum over the 64 lanes of a wavefront; *total gets the
-// sum of all lanes.
+// sum of all lanes.  DPP row shifts scan each 16-lane row, then the last
+// lane of row 0 / row 1 is broadcast into rows 1 and 3 / 2 and 3.
 __device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t x, uint32_t *total) {
-    const int lane = (int)(threadIdx.x & 63);
-    uint32_t incl = x;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t t = (uint32_t)__shfl_up((int)incl, off, 64);
-        if (lane >= off) incl += t;
-    }
-    *total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    return incl - x;
+    uint32_t v = x;
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    *total = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+    return v - x;
 }
 
 // A value every lane holds identically, moved to scalar registers.
@@ -623,12 +624,14 @@ __device__ __forceinline__ void sweep_bands(uint32_t *par, const uint64_t *msk, 
         uint32_t *pn = &par[node];
         if (lane_in(S)) {
             // the interval's smallest pixel: its first top-row pixel, else
-            // its first bottom-row pixel
-            const uint64_t from = ~0ull << lane;
-            const uint64_t span = from & ((2ull << __builtin_ctzll(E & from)) - 1ull);
-            const uint64_t tt = t & span;
-            const uint32_t row = (uint32_t)(2 * band) + (tt ? 0u : 1u);
-            const uint32_t col = (uint32_t)__builtin_ctzll(tt ? tt : (b & span));
+            // its first pixel (a bottom-row one, at the start column); the
+            // first top-row pixel at or after the start belongs to the
+            // interval when no interval ends before it
+            const uint64_t tf = t & (~0ull << lane);
+            const uint64_t ft = tf & (0ull - tf);  // lowest bit of tf (0 if none)
+            const bool top = ft != 0ull && (E & (ft - 1ull) & (~0ull << lane)) == 0ull;
+            const uint32_t row = (uint32_t)(2 * band) + (top ? 0u : 1u);
+            const uint32_t col = top ? (uint32_t)__builtin_ctzll(ft) : (uint32_t)lane;
             lds_st(pn, (((row << 6) | col) << kNodeBits) | node);
         }
         uint32_t md = kNone;
