@@ -187,6 +187,19 @@ def bench_batch(args, torch, binding, log):
             ctx.close()
     ctx = graph_ctx
     ms_batch = ms_by_mode[True]
+    # the same context autotuned on this batch (ccl_ctx_autotune), graph replay
+    default_cfg = ctx.config(args.conn)
+    tuned_cfg, _ = ctx.autotune(d_imgs, args.conn, reps=2, outs=outs)
+    for _ in range(3):
+        ctx.label(d_imgs, args.conn, outs=outs, descs=descs)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        ctx.label(d_imgs, args.conn, outs=outs, descs=descs)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms_tuned = a.elapsed_time(b) / reps
+    log("[bench] batch: default %s %.3f ms, autotuned %s %.3f ms" % (default_cfg, ms_batch, tuned_cfg, ms_tuned))
     # plain path: one ccl_label_2d per image, back to back on one stream
     calls = [(im.data_ptr(), im.shape[0], im.shape[1], im.shape[1], args.conn, o.data_ptr(), sh)
              for im, o in zip(d_imgs, outs)]
@@ -207,7 +220,10 @@ def bench_batch(args, torch, binding, log):
            "batched_gpix_s": round(px / ms_batch / 1e6, 2),
            "plain_ms": round(ms_plain, 4), "plain_fps": round(len(imgs) / ms_plain * 1e3, 1),
            "plain_gpix_s": round(px / ms_plain / 1e6, 2),
-           "speedup_vs_plain": round(ms_plain / ms_batch, 3)}
+           "speedup_vs_plain": round(ms_plain / ms_batch, 3),
+           "default_tiles": list(default_cfg), "autotuned_tiles": list(tuned_cfg),
+           "autotuned_ms": round(ms_tuned, 4), "autotuned_fps": round(len(imgs) / ms_tuned * 1e3, 1),
+           "autotuned_speedup_vs_default": round(ms_batch / ms_tuned, 3)}
     if not args.no_cpu_baseline:
         import oracle
         from concurrent.futures import ThreadPoolExecutor

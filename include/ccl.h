@@ -255,8 +255,9 @@ typedef struct ccl_image_desc {
  * max_pixels  most pixels per call, summed over images (>= 1); the tile
  *             workspace is sized for it with room for partial tiles.
  * cfg         tile configuration for every call ({0,0} = the library's
- *             choice for one image of max_pixels pixels: a call's grid
- *             covers the tiles of all its images).
+ *             choice per connectivity for one image of max_pixels pixels,
+ *             since a call's grid covers the tiles of all its images; it
+ *             can then be retuned with ccl_ctx_autotune).
  * use_graph   nonzero: build one three-node hipGraph per connectivity and
  *             replay it; when a call's grids or arguments differ from the
  *             previous call's, the nodes are updated first (after waiting
@@ -296,6 +297,28 @@ int ccl_ctx_destroy(ccl_ctx *ctx);
  */
 int ccl_label_batch(ccl_ctx *ctx, const ccl_image_desc *descs, int32_t n, int32_t connectivity,
                     void *stream);
+
+/* Tile configuration the context uses for `connectivity` (4 or 8): the one
+ * it was created with, or the autotuner's choice.  Writes *out. */
+int ccl_ctx_config(const ccl_ctx *ctx, int32_t connectivity, ccl_config *out);
+
+/*
+ * ccl_ctx_autotune -- choose the context's tile configuration for one
+ * connectivity by timing the batch `descs` (n images, as in
+ * ccl_label_batch) under every compiled configuration that fits the
+ * context, `reps` calls each after one warm-up call on `stream`, and keep
+ * the fastest for the context's later calls with that connectivity.  The
+ * images' labels are overwritten (the last call leaves valid labels).
+ * Blocks until the timing is done.  *best / *best_ms (either may be NULL)
+ * receive the winner and its mean milliseconds per call.  A context
+ * created with an explicit cfg keeps it: CCL_ERR_UNSUPPORTED.  Other
+ * errors as ccl_label_batch; on error the previous configuration stays.
+ * The workspace of a context created without a cfg is sized at creation
+ * for every configuration (the largest need over tile heights), so tuning
+ * never allocates.
+ */
+int ccl_ctx_autotune(ccl_ctx *ctx, const ccl_image_desc *descs, int32_t n, int32_t connectivity,
+                     int32_t reps, void *stream, ccl_config *best, float *best_ms);
 
 /* ----------------------------------------------------------------- serve
  *

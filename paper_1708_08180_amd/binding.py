@@ -75,6 +75,9 @@ SIGNATURES = {
     "ccl_ctx_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(CtxOpts)]),
     "ccl_ctx_destroy": (ctypes.c_int, [_P]),
     "ccl_label_batch": (ctypes.c_int, [_P, ctypes.POINTER(ImageDesc), _I32, _I32, _P]),
+    "ccl_ctx_config": (ctypes.c_int, [_P, _I32, ctypes.POINTER(Config)]),
+    "ccl_ctx_autotune": (ctypes.c_int, [_P, ctypes.POINTER(ImageDesc), _I32, _I32, _I32, _P,
+                                        ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_float)]),
     "ccl_autotune": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, _I32, _P, ctypes.POINTER(Config),
                                     ctypes.POINTER(ctypes.c_float)]),
     "ccl_tuning_get": (ctypes.c_int, [_I32, _I32, _I32, ctypes.POINTER(Config)]),
@@ -409,6 +412,25 @@ class BatchContext:
                                              _stream_handle(stream))
         _check(rc, "ccl_label_batch")
         return outs
+
+    def config(self, conn: int = 8):
+        """(tile_h, waves) the context uses for this connectivity."""
+        cfg = Config()
+        _check(load_library().ccl_ctx_config(self._h, int(conn), ctypes.byref(cfg)), "ccl_ctx_config")
+        return (cfg.tile_h, cfg.waves)
+
+    def autotune(self, images, conn: int = 8, reps: int = 3, outs=None, stream=None):
+        """Time every tile configuration on this batch and keep the fastest
+        for `conn` (ccl_ctx_autotune); returns ((tile_h, waves), ms per call)."""
+        torch = _torch()
+        if outs is None:
+            outs = [torch.empty(tuple(im.shape), dtype=torch.int32, device=im.device) for im in images]
+        descs = self.descs(images, outs)
+        best, ms = Config(), ctypes.c_float()
+        _check(load_library().ccl_ctx_autotune(self._h, descs, len(images), int(conn), int(reps),
+                                               _stream_handle(stream), ctypes.byref(best), ctypes.byref(ms)),
+               "ccl_ctx_autotune")
+        return (best.tile_h, best.waves), float(ms.value)
 
 
 def label_batch(images, conn: int = 8, ctx: BatchContext = None, stream=None):

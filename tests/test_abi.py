@@ -185,3 +185,10 @@ def test_noalloc_limit_covers_4096_square():
     assert 0 < size.value <= limit
     assert lib.ccl_workspace_size(8192, 8192, None, ctypes.byref(size)) == 0
     assert size.value > limit
+
+
+def test_ctx_autotune_validation_without_device():
+    lib = binding.load_library()
+    cfg = binding.Config()
+    assert lib.ccl_ctx_config(None, 8, ctypes.byref(cfg)) == 1
+    assert lib.ccl_ctx_autotune(None, None, 1, 8, 1, None, None, None) == 1

@@ -165,3 +165,38 @@ def test_batch_mixed_workload_sizes(conn):
         want = oracle.label(im, conn)
         assert np.array_equal(g, want), "image %d (%dx%d) differs" % (k, im.shape[0], im.shape[1])
     ctx.close()
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_autotune_per_connectivity(use_graph):
+    """ccl_ctx_autotune times every configuration on the batch, keeps the
+    fastest per connectivity, and the context's later calls (switched
+    kernels, rebuilt graphs) still equal the oracle on every image."""
+    import torch
+
+    ctx = binding.BatchContext(48, 48 * 480 * 640, use_graph=use_graph)
+    imgs = _mixed_images(40, 21)
+    d = [torch.from_numpy(np.ascontiguousarray(im)).cuda() for im in imgs]
+    for conn in (8, 4):
+        before = ctx.config(conn)
+        best, ms = ctx.autotune(d, conn, reps=2)
+        say("autotune conn=%d graph=%s: %s -> %s (%.3f ms)" % (conn, use_graph, before, best, ms))
+        assert ms > 0 and ctx.config(conn) == best
+        assert best in {(t, w) for t in (16, 32, 64, 128) for w in (1, 2, 4, 8, 16)}
+        for seed in (22, 23):
+            batch = _mixed_images(30 + seed % 7, seed)
+            got = _run(ctx, batch, conn)
+            for k, (im, g) in enumerate(zip(batch, got)):
+                assert np.array_equal(g, oracle.label(im, conn)), "conn %d image %d differs" % (conn, k)
+    ctx.close()
+
+
+def test_batch_autotune_keeps_a_fixed_config():
+    import torch
+
+    ctx = binding.BatchContext(8, 8 * 240 * 320, config=(32, 4))
+    d = [torch.from_numpy(np.ascontiguousarray(im)).cuda() for im in _mixed_images(4, 24)]
+    with pytest.raises(binding.CclError):
+        ctx.autotune(d, 8)
+    assert ctx.config(8) == (32, 4) and ctx.config(4) == (32, 4)
+    ctx.close()
