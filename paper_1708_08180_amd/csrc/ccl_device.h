@@ -231,20 +231,25 @@ __device__ __forceinline__ void lds_link(uint32_t *par, uint32_t a, uint32_t b) 
 
 // ------------------------------------------------------ global union-find
 
+// Find steps after which a join also points its starting nodes at the root.
+constexpr uint32_t kLongWalk = 256u;
+
 // Roots of a and b in the global forest, found together so that the loads
 // of both walks are in flight at once.  Path halving: a node whose parent
 // is not a root is pointed at its grandparent with an atomicMin, which can
-// only lower a parent to an ancestor.
-__device__ __forceinline__ void g_find2(uint32_t *L, uint32_t &a, uint32_t &b) {
-    bool ra = false, rb = false;
+// only lower a parent to an ancestor.  steps counts the loop's passes.
+__device__ __forceinline__ void g_find2(uint32_t *L, uint32_t &a, uint32_t &b, uint32_t &steps) {
+    // every step issues both walks' loads unconditionally (a root re-reads
+    // its own entry), so the two loads are in flight together and the
+    // wavefront waits once per step
     while (true) {
-        const uint32_t pa = ra ? a : g_ld(&L[a]) - 1u;
-        const uint32_t pb = rb ? b : g_ld(&L[b]) - 1u;
-        ra = ra || pa >= a;
-        rb = rb || pb >= b;
+        ++steps;
+        uint32_t pa = g_ld(&L[a]) - 1u, pb = g_ld(&L[b]) - 1u;
+        bool ra = pa >= a, rb = pb >= b;
         if (ra && rb) return;
-        const uint32_t ga = ra ? pa : g_ld(&L[pa]) - 1u;
-        const uint32_t gb = rb ? pb : g_ld(&L[pb]) - 1u;
+        pa = ra ? a : pa;
+        pb = rb ? b : pb;
+        const uint32_t ga = g_ld(&L[pa]) - 1u, gb = g_ld(&L[pb]) - 1u;
         if (!ra) {
             if (ga >= pa) {
                 a = pa;
@@ -271,15 +276,27 @@ __device__ __forceinline__ void g_find2(uint32_t *L, uint32_t &a, uint32_t &b) {
 // When the atomicMin shows that b stopped being a root meanwhile, the value
 // it returns is b's new parent and the link is retried from there, so no
 // concurrent link is lost.
+//
+// A join whose walks took many steps (a long chain, as a spiral or a
+// serpentine builds across tiles) points both of its starting nodes straight
+// at the final root, so the next join along the same chain starts next to
+// the root instead of walking it again.  Path halving alone only halves such
+// a chain per walk.  Joins that found their roots quickly skip this.
 __device__ __forceinline__ void g_union(uint32_t *L, uint32_t n, uint32_t a, uint32_t b) {
     if (a >= n || b >= n) return;
+    const uint32_t a0 = a, b0 = b;
+    uint32_t steps = 0;
     while (true) {
-        g_find2(L, a, b);
-        if (a == b) return;
+        g_find2(L, a, b, steps);
+        if (a == b) break;
         if (a > b) { const uint32_t t = a; a = b; b = t; }
         const uint32_t old = g_min(&L[b], a + 1u) - 1u;
-        if (old >= b) return;
+        if (old >= b) break;
         b = old;
+    }
+    if (steps > kLongWalk) {
+        g_min(&L[a0], a + 1u);
+        g_min(&L[b0], a + 1u);
     }
 }
 
