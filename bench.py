@@ -309,6 +309,17 @@ def bench_extensions(img, conn, torch, binding, reps=50):
     sh = ctypes.c_void_p(stream.cuda_stream)
     ms_st = timed(lambda: lib.ccl_component_stats(lab.data_ptr(), H, W, recs.data_ptr(), n,
                                                   n_dev.data_ptr(), sh))
+    # labels and statistics in one call (the link gathers the statistics),
+    # against the plain labeling call on the same stream
+    pitch = W
+    ms_plain = timed(lambda: lib.ccl_label_2d(d.data_ptr(), H, W, pitch, conn, lab.data_ptr(), sh))
+    lab_f = torch.empty_like(lab)
+    recs_f = torch.empty_like(recs)
+    n_f = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ms_fused = timed(lambda: lib.ccl_label_2d_stats(d.data_ptr(), H, W, pitch, conn, lab_f.data_ptr(),
+                                                     recs_f.data_ptr(), n, n_f.data_ptr(), None, sh))
+    torch.cuda.synchronize()
+    same = bool(int(n_f.item()) == n and torch.equal(lab_f, lab) and torch.equal(recs_f, recs))
     # 3D: 256^3 voxels, Bernoulli(0.3) (percolating under 26-connectivity)
     vol_h = (wl_rng(2300).random((256, 256, 256)) < 0.3).astype("uint8")
     vol = torch.from_numpy(vol_h).cuda()
@@ -321,7 +332,13 @@ def bench_extensions(img, conn, torch, binding, reps=50):
                                      "note": "every value class of the same image, background included"},
             "component_stats": {"ms": round(ms_st, 5), "components": n,
                                 "gpix_s": round(px / ms_st / 1e6, 2),
-                                "note": "area, bounding box, coordinate sums of every component of its labels"}}
+                                "note": "area, bounding box, coordinate sums of every component of its labels"},
+            "labels_with_stats": {"ms": round(ms_fused, 5), "plain_labels_ms": round(ms_plain, 5),
+                                  "ratio_vs_plain": round(ms_fused / ms_plain, 3),
+                                  "gpix_s": round(px / ms_fused / 1e6, 2),
+                                  "same_as_two_step": same,
+                                  "note": "ccl_label_2d_stats: labels and every component's statistics in one "
+                                          "call, against ccl_label_2d alone"}}
 
 
 def make_workload(name):

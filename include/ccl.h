@@ -212,6 +212,31 @@ int ccl_component_stats(const uint32_t *labels, int32_t H, int32_t W, ccl_compon
                         int64_t capacity, uint32_t *n_out, void *stream);
 
 /*
+ * ccl_label_2d_stats -- ccl_label_2d and ccl_component_stats in one call:
+ * the link phase (Sec. II-C) also accumulates each component's area,
+ * bounding box and coordinate sums while it holds every pixel's final root,
+ * so the labels are not read back.
+ * img, H, W, pitch, connectivity, labels   as for ccl_label_2d (binary).
+ * out, capacity, n_out   as for ccl_component_stats: record k is the
+ *           component with the k-th smallest label; the first `capacity`
+ *           records are written (capacity 0: count only); *n_out = the
+ *           number of components.
+ * stream    hipStream_t; asynchronous.  Uses the per-stream workspace of
+ *           ccl_label_2d plus about 0.3 bytes per pixel and 16 bytes per
+ *           possible tile-local component (at most one per 2 x 2 pixels
+ *           under 8-connectivity, one per 2 pixels under 4-connectivity).
+ * cfg       tile configuration, or NULL / {0, 0}: the tuning table's for
+ *           (H, W, connectivity), with tiles of more than 64 rows replaced
+ *           by (64, 4).  Tiles of more than 64 rows are not compiled for
+ *           this entry point (CCL_ERR_UNSUPPORTED).
+ * Errors: as ccl_label_2d; CCL_ERR_INVALID_ARG also for a null n_out,
+ * capacity < 0, or capacity > 0 with a null out.
+ */
+int ccl_label_2d_stats(const uint8_t *img, int32_t H, int32_t W, int64_t pitch, int32_t connectivity,
+                       uint32_t *labels, ccl_component *out, int64_t capacity, uint32_t *n_out,
+                       const ccl_config *cfg, void *stream);
+
+/*
  * ccl_label_3d -- label a binary volume (the method on a 3D grid).
  * vol     DEVICE, D slices of H rows of W voxels: voxel (z, y, x) at
  *         vol[z * pitch_z + y * pitch_y + x]; nonzero = foreground.

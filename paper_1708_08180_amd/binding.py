@@ -70,6 +70,8 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_float)]),
     "ccl_label_2d_equal": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, ctypes.POINTER(Config), _P]),
     "ccl_component_stats": (ctypes.c_int, [_P, _I32, _I32, _P, _I64, _P, _P]),
+    "ccl_label_2d_stats": (ctypes.c_int, [_P, _I32, _I32, _I64, _I32, _P, _P, _I64, _P,
+                                          ctypes.POINTER(Config), _P]),
     "ccl_label_3d": (ctypes.c_int, [_P, _I32, _I32, _I32, _I64, _I64, _I32, _P, _P]),
     "ccl_shutdown": (None, []),
     "ccl_ctx_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(CtxOpts)]),
@@ -310,6 +312,36 @@ def component_stats(labels, capacity: int = None, stream=None):
     n = int(n_dev.cpu().numpy().view(np.uint32)[0])
     rec = out.cpu().numpy()[:min(n, capacity) * COMPONENT_BYTES].view(np.dtype(COMPONENT_DTYPE))
     return rec
+
+
+def label_stats(img, conn: int = 8, capacity: int = None, out=None, config=None, stream=None):
+    """Labels and per-component statistics of a 2D uint8 device image in
+    one call (ccl_label_2d_stats): returns (labels int32 tensor, numpy
+    structured array of records in increasing label order).  With capacity
+    None the image is labeled once to count the components (one
+    synchronization), then again with room for all of them."""
+    import numpy as np
+
+    torch = _torch()
+    _check_image(img)
+    H, W = img.shape
+    out = _check_out(out, img)
+    lib = load_library()
+    cfg = ctypes.byref(Config(int(config[0]), int(config[1]))) if config else None
+    n_dev = torch.zeros(1, dtype=torch.int32, device=img.device)
+    with torch.cuda.device(img.device):
+        if capacity is None:
+            _check(lib.ccl_label_2d_stats(img.data_ptr(), H, W, _pitch(img), int(conn), out.data_ptr(),
+                                          None, 0, n_dev.data_ptr(), cfg, _stream_handle(stream)),
+                   "ccl_label_2d_stats")
+            capacity = int(n_dev.cpu().numpy().view(np.uint32)[0])
+        recs = torch.empty(max(1, capacity) * COMPONENT_BYTES, dtype=torch.uint8, device=img.device)
+        _check(lib.ccl_label_2d_stats(img.data_ptr(), H, W, _pitch(img), int(conn), out.data_ptr(),
+                                      recs.data_ptr() if capacity else None, int(capacity),
+                                      n_dev.data_ptr(), cfg, _stream_handle(stream)), "ccl_label_2d_stats")
+    n = int(n_dev.cpu().numpy().view(np.uint32)[0])
+    rec = recs.cpu().numpy()[:min(n, capacity) * COMPONENT_BYTES].view(np.dtype(COMPONENT_DTYPE))
+    return out, rec
 
 
 def label3d(vol, conn: int = 26, out=None, stream=None):

@@ -35,6 +35,10 @@ bool config_supported_equal(int th, int nw);
 hipError_t launch_plain(const ImgView &v, int th, int nw, int conn, hipStream_t s,
                         hipEvent_t *ev = nullptr, bool equal = false);
 
+// The local merge and the boundary analysis of binary labeling for one
+// image on `s`, without the link.
+hipError_t launch_merge(const ImgView &v, int th, int nw, int conn, hipStream_t s);
+
 // Workspace layout for one image: edge masks, edge-cell roots, row masks
 // (row foreground and edge-root masks), run slots.
 struct WsLayout {

@@ -23,6 +23,7 @@
 
 #include "ccl_device.h"
 #include "ccl_internal.h"
+#include "ccl_link.h"
 
 namespace ccl {
 
@@ -425,140 +426,6 @@ __device__ __forceinline__ void k2_tile_eq(const ImgView &v, uint32_t t) {
     union_requests<6>(A, B, [&](uint32_t a, uint32_t b) { g_union(v.labels, v.n, a, b); });
 }
 
-// ----------------------------------------------------------------- link
-
-// Link body for tile t (Sec. II-C): the local merge left the tile's row
-// masks, the masks of its local roots whose components touch a shared tile
-// edge ("flagged" roots), and per run its tile-local root pixel.  Every
-// local root pixel first puts its final label - 1 into fin[]: unflagged
-// roots are already final; flagged roots are resolved in the global forest
-// (where a tile's stores of final labels compress the paths of the tiles
-// that still walk through its pixels).  A wavefront lists the flagged roots of
-// its rows in LDS and resolves them all at once, one per lane, so their
-// walks overlap instead of following each other row by row.  Then every
-// pixel reads its root's entry; output rows are full 256-byte lines.  Ends
-// after a workgroup barrier.
-//
-// A flagged root is the root of some edge cell, so a tile has at most
-// roots_per_tile(TH) of them; `flist` holds that many entries per wavefront.
-
-// `rw` / `sl`: the tile's row data and run records in the workspace (they
-// depend on the tile only, so their loads need not wait for the image's
-// descriptor in the batched form).
-template <int TH, int NW, bool EQ>
-__device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, const uint64_t *rw,
-                                        const uint16_t *sl, uint32_t *fin, uint16_t *flist) {
-    constexpr int kFlagCap = roots_per_tile(TH);
-    constexpr int SPR = slots_per_row<EQ>();
-    constexpr int RPW = TH / NW;
-    const uint32_t TX = (uint32_t)v.tilesX;
-    const uint32_t tx = t % TX, ty = t / TX;
-    const int lane = lane_id();
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const uint32_t W = (uint32_t)v.W;
-    const uint64_t *rm = rw + wave * RPW;
-    // global index of the tile's pixel (0, 0); every label fits in 32 bits
-    const uint32_t origin = ty * (uint32_t)TH * W + tx * (uint32_t)kTileW;
-    // equal-value: every in-image pixel takes part (rows hold run starts)
-    const int wlim = min(kTileW, v.W - (int)tx * kTileW);
-    const uint64_t cols = wlim == 64 ? ~0ull : ((1ull << wlim) - 1ull);
-    const int rows_in = v.H - (int)ty * TH - wave * RPW;
-    // first record of this wave's rows or bands (lane k: row or band k of
-    // the wave): equal-value records have 64 slots per row; binary records
-    // are numbered densely by two-row band, and the local merge stored every
-    // band's first record (a wavefront owns whole bands)
-    static_assert(EQ || RPW % 2 == 0, "a wavefront owns whole bands");
-    constexpr int BPW = EQ ? 1 : RPW / 2;
-    uint32_t rbv;
-    if (EQ) {
-        rbv = (uint32_t)((wave * RPW + lane) * SPR);
-    } else {
-        const uint16_t *rbg = (const uint16_t *)(rw + rowmask_bases(TH));
-        rbv = lane < BPW ? (uint32_t)rbg[wave * BPW + lane] : 0u;
-    }
-    uint64_t m[RPW], f[RPW], be[BPW];
-    // records: one per row (equal-value) or one per band, which both rows
-    // of the band share (binary)
-    constexpr int NR = EQ ? RPW : BPW;
-    uint32_t rec[NR];
-#pragma unroll
-    for (int k = 0; k < RPW; ++k) {
-        m[k] = uniform64(rm[k]);
-        f[k] = uniform64(rm[TH + k]);
-    }
-    if (!EQ) {
-#pragma unroll
-        for (int k = 0; k < BPW; ++k) be[k] = uniform64(rw[rowmask_ends(TH) + wave * BPW + k]);
-    }
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        // this lane's node (background lanes read some record of the tile
-        // and discard it): equal-value, the rank among the row's run
-        // starts at or below it; binary, the band's intervals ending before
-        // it (lanes right of the band's last interval take that interval)
-        uint32_t node;
-        uint64_t d;
-        if (EQ) {
-            const uint64_t S = m[i];
-            const uint32_t below = bits_below(S) + (lane_in(S) ? 1u : 0u);
-            node = (uint32_t)__builtin_amdgcn_readlane((int)rbv, i) + (below ? below - 1u : 0u);
-            d = i < rows_in ? cols : 0ull;
-        } else {
-            const uint64_t E = be[i];
-            const uint32_t below = bits_below(E), last = (uint32_t)__popcll(E);
-            node = (uint32_t)__builtin_amdgcn_readlane((int)rbv, i) + (below < last ? below : (last ? last - 1u : 0u));
-            d = m[2 * i] | m[2 * i + 1];
-        }
-        const uint32_t r = sl[node];
-        rec[i] = lane_in(d) ? r : kNone;
-    }
-    // this wave's flagged roots, listed in row order
-    uint16_t *fl = flist + wave * kFlagCap;
-    uint32_t nf = 0;
-#pragma unroll
-    for (int k = 0; k < RPW; ++k) {
-        const uint32_t pos = nf + bits_below(f[k]);
-        if (lane_in(f[k]) && pos < (uint32_t)kFlagCap)
-            fl[pos] = (uint16_t)((wave * RPW + k) * kTileW + lane);
-        nf += (uint32_t)__popcll(f[k]);
-    }
-    nf = min(nf, (uint32_t)kFlagCap);
-    // unflagged local roots are final
-#pragma unroll
-    for (int k = 0; k < RPW; ++k) {
-        const uint32_t l = (uint32_t)((wave * RPW + k) * kTileW + lane);
-        if (rec[EQ ? k : k / 2] == l && !lane_in(f[k])) fin[l] = origin + (l >> 6) * W + (l & 63u);
-    }
-    // the list is read back by other lanes of this wavefront
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    for (uint32_t i = (uint32_t)lane; i < nf; i += 64u) {
-        const uint32_t l = fl[i];
-        fin[l] = g_root(v.labels, origin + (l >> 6) * W + (l & 63u));
-    }
-    __syncthreads();
-    const uint32_t x = tx * (uint32_t)kTileW + (uint32_t)lane;
-    const uint32_t y0 = ty * (uint32_t)TH + (uint32_t)(wave * RPW);
-    uint32_t *out = v.labels + origin + (uint32_t)(wave * RPW) * W + (uint32_t)lane;
-    const bool full = (tx + 1u) * kTileW <= W && y0 + RPW <= (uint32_t)v.H;
-    // streaming stores: the output is not read again here, and keeping it
-    // out of the L2 leaves the records and the forest cached for the tiles
-    // still to run (a stale cached label is an ancestor)
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        const uint32_t val = rec[i] != kNone ? fin[rec[i] & (TH * kTileW - 1)] + 1u : 0u;
-        if (EQ) {
-            if (full || (x < W && y0 + i < (uint32_t)v.H)) __builtin_nontemporal_store(val, &out[(size_t)i * W]);
-        } else {
-            const int k = 2 * i;
-            const uint32_t v0 = lane_in(m[k]) ? val : 0u, v1 = lane_in(m[k + 1]) ? val : 0u;
-            if (full || (x < W && y0 + k < (uint32_t)v.H)) __builtin_nontemporal_store(v0, &out[(size_t)k * W]);
-            if (full || (x < W && y0 + k + 1 < (uint32_t)v.H)) __builtin_nontemporal_store(v1, &out[(size_t)(k + 1) * W]);
-        }
-    }
-    __syncthreads();
-}
-
 // ------------------------------------------------------ single-image kernels
 
 template <int TH, int NW, bool CONN8, bool EQ>
@@ -652,13 +519,6 @@ __global__ void __launch_bounds__(NW * 64) k3_batch(BatchArgs a) {
 
 // ---------------------------------------------------------------- launchers
 
-// Waves per workgroup of the link kernel: 16 rows per wave whatever the
-// local merge uses (measured best at 32 and 64 rows per tile).
-template <int TH>
-constexpr int link_waves() {
-    return TH / 16;
-}
-
 template <int TH, int NW, bool CONN8, bool EQ>
 static hipError_t launch_plain_t(const ImgView &v, hipStream_t stream, hipEvent_t *ev) {
     const uint32_t tiles = (uint32_t)v.tilesX * (uint32_t)v.tilesY;
@@ -672,6 +532,18 @@ static hipError_t launch_plain_t(const ImgView &v, hipStream_t stream, hipEvent_
     constexpr int NW3 = link_waves<TH>();
     hipLaunchKernelGGL((k3_link<TH, NW3, EQ>), dim3(tiles), dim3(NW3 * 64), 0, stream, v);
     if (ev) (void)hipEventRecord(ev[3], stream);
+    return hipGetLastError();
+}
+
+// Local merge and boundary analysis only (binary labeling): the phases
+// before a link kernel that the caller launches.
+template <int TH, int NW, bool CONN8>
+static hipError_t launch_merge_t(const ImgView &v, hipStream_t stream) {
+    const uint32_t tiles = (uint32_t)v.tilesX * (uint32_t)v.tilesY;
+    hipLaunchKernelGGL((k1_local_merge<TH, NW, CONN8, false>), dim3(tiles), dim3(NW * 64), 0, stream, v);
+    if (tiles > 1)
+        hipLaunchKernelGGL((k2_boundary<TH, CONN8, false>), dim3((tiles + 3) / 4), dim3(256), 0, stream,
+                           v, tiles);
     return hipGetLastError();
 }
 
@@ -726,6 +598,15 @@ hipError_t launch_plain(const ImgView &v, int th, int nw, int conn, hipStream_t 
     if (th == T && nw == N)                                                   \
         return conn == 8 ? launch_plain_t<T, N, true, false>(v, s, ev)        \
                          : launch_plain_t<T, N, false, false>(v, s, ev);
+    CCL_FOR_EACH_CONFIG(CCL_CASE)
+#undef CCL_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_merge(const ImgView &v, int th, int nw, int conn, hipStream_t s) {
+#define CCL_CASE(T, N)                                                        \
+    if (th == T && nw == N)                                                   \
+        return conn == 8 ? launch_merge_t<T, N, true>(v, s) : launch_merge_t<T, N, false>(v, s);
     CCL_FOR_EACH_CONFIG(CCL_CASE)
 #undef CCL_CASE
     return hipErrorInvalidValue;

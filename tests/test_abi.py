@@ -192,3 +192,28 @@ def test_ctx_autotune_validation_without_device():
     cfg = binding.Config()
     assert lib.ccl_ctx_config(None, 8, ctypes.byref(cfg)) == 1
     assert lib.ccl_ctx_autotune(None, None, 1, 8, 1, None, None, None) == 1
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, 4, 4, 4, 8, FAKE, FAKE, 1, FAKE, None, None), 1),      # null image
+    ((FAKE, 4, 4, 4, 8, None, FAKE, 1, FAKE, None, None), 1),      # null labels
+    ((FAKE, 4, 4, 4, 8, FAKE, FAKE, 1, None, None, None), 1),      # null count
+    ((FAKE, 4, 4, 4, 8, FAKE, None, 1, FAKE, None, None), 1),      # capacity without records
+    ((FAKE, 4, 4, 4, 8, FAKE, FAKE, -1, FAKE, None, None), 1),     # capacity < 0
+    ((FAKE, 4, 8, 7, 8, FAKE, FAKE, 1, FAKE, None, None), 1),      # pitch < W
+    ((FAKE, 4, 4, 4, 6, FAKE, FAKE, 1, FAKE, None, None), 2),      # connectivity 6
+    ((FAKE, 65536, 65537, 65537, 8, FAKE, FAKE, 1, FAKE, None, None), 3),  # H*W > 2^32-1
+])
+def test_label_stats_invalid_arguments(args, code):
+    """The labels-with-statistics entry point validates like ccl_label_2d
+    and ccl_component_stats, before touching the device."""
+    lib = binding.load_library()
+    assert lib.ccl_label_2d_stats(*args) == code
+
+
+def test_label_stats_config_validation():
+    # tiles of more than 64 rows, and configurations not compiled at all
+    lib = binding.load_library()
+    for th, nw in ((128, 4), (128, 8), (48, 4), (64, 3)):
+        cfg = binding.Config(th, nw)
+        assert lib.ccl_label_2d_stats(FAKE, 64, 64, 64, 8, FAKE, FAKE, 1, FAKE, ctypes.byref(cfg), None) == 2
