@@ -30,8 +30,9 @@
  *     Work is enqueued asynchronously; the caller synchronizes.
  *   - Every entry point validates all arguments before enqueuing anything
  *     and returns a ccl_status.  No exception crosses the ABI.
- *   - img and labels must not overlap.  The caller owns all buffers it
- *     passes; the library never frees them.
+ *   - img and labels must not overlap: an entry point whose image (or
+ *     volume) bytes and label bytes intersect returns CCL_ERR_INVALID_ARG.
+ *     The caller owns all buffers it passes; the library never frees them.
  *   - The contents of `labels` on entry are ignored; the buffer is fully
  *     overwritten.  It also serves as the union-find forest while the call
  *     runs, so it must not be read until the work on `stream` completes.

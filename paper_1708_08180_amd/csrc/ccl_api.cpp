@@ -90,10 +90,26 @@ void release_stream_workspaces() {
     g_ws.clear();
 }
 
-int validate_image(const void *img, int32_t H, int32_t W, int64_t pitch, const void *labels) {
-    if (!img || !labels) return CCL_ERR_INVALID_ARG;
+int validate_image_only(const void *img, int32_t H, int32_t W, int64_t pitch) {
+    if (!img) return CCL_ERR_INVALID_ARG;
     if (H <= 0 || W <= 0 || pitch < (int64_t)W) return CCL_ERR_INVALID_ARG;
     if ((uint64_t)H * (uint64_t)W > 0xFFFFFFFFull) return CCL_ERR_TOO_LARGE;
+    return CCL_OK;
+}
+
+bool byte_ranges_overlap(const void *a, unsigned __int128 na, const void *b, unsigned __int128 nb) {
+    const unsigned __int128 pa = (uintptr_t)a, pb = (uintptr_t)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+int validate_image(const void *img, int32_t H, int32_t W, int64_t pitch, const void *labels) {
+    const int rc = validate_image_only(img, H, W, pitch);
+    if (rc != CCL_OK) return rc;
+    if (!labels) return CCL_ERR_INVALID_ARG;
+    // the image's bytes (its last row ends at W) against the labels' u32s
+    const unsigned __int128 img_bytes = (unsigned __int128)(H - 1) * (uint64_t)pitch + (uint64_t)W;
+    const unsigned __int128 lab_bytes = (unsigned __int128)H * (uint64_t)W * 4u;
+    if (byte_ranges_overlap(img, img_bytes, labels, lab_bytes)) return CCL_ERR_INVALID_ARG;
     return CCL_OK;
 }
 

@@ -74,7 +74,14 @@ int fail_hip(hipError_t e);
 int stream_workspace(hipStream_t s, size_t need, void **out, std::unique_lock<std::mutex> *held);
 // Frees the cached workspace of (current device, s), in stream order on s.
 void release_stream_workspace(hipStream_t s);
+// Image arguments: a non-null image of H x W >= 1 bytes per row pitch >= W
+// and H * W <= 2^32 - 1.
+int validate_image_only(const void *img, int32_t H, int32_t W, int64_t pitch);
+// The same, and a non-null label buffer of H * W u32 whose bytes do not
+// overlap the image's.
 int validate_image(const void *img, int32_t H, int32_t W, int64_t pitch, const void *labels);
+// True when [a, a + na) and [b, b + nb) share a byte.
+bool byte_ranges_overlap(const void *a, unsigned __int128 na, const void *b, unsigned __int128 nb);
 int resolve_config(int H, int W, int conn, const ccl_config *cfg, int *th, int *nw);
 void default_config(int H, int W, int conn, int *th, int *nw);
 // The kernels' view of one image whose workspace (ws_layout(H, W, th,

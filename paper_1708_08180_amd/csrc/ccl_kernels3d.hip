@@ -282,6 +282,9 @@ extern "C" int ccl_label_3d(const uint8_t *vol, int32_t D, int32_t H, int32_t W,
     if (connectivity != 6 && connectivity != 18 && connectivity != 26) return CCL_ERR_UNSUPPORTED;
     const uint64_t n = (uint64_t)D * (uint64_t)H * (uint64_t)W;
     if (n > 0xFFFFFFFFull) return CCL_ERR_TOO_LARGE;
+    const unsigned __int128 vol_bytes = (unsigned __int128)(D - 1) * (uint64_t)pitch_z +
+                                        (unsigned __int128)(H - 1) * (uint64_t)pitch_y + (uint64_t)W;
+    if (byte_ranges_overlap(vol, vol_bytes, labels, (unsigned __int128)n * 4u)) return CCL_ERR_INVALID_ARG;
     Vol v;
     v.vol = vol;
     v.labels = labels;

@@ -257,7 +257,7 @@ int ccl_server_slots(const ccl_server *s, int32_t *n_slots) {
 int ccl_server_submit(ccl_server *s, const uint8_t *img, int32_t H, int32_t W, int64_t pitch,
                       uint64_t tag) {
     if (!s) return CCL_ERR_INVALID_ARG;
-    const int rc = validate_image(img, H, W, pitch, img);
+    const int rc = validate_image_only(img, H, W, pitch);
     if (rc != CCL_OK) return rc;
     if ((int64_t)H * W > s->opts.max_frame_pixels) return CCL_ERR_CAPACITY;
     Frame f{};

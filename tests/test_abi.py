@@ -41,16 +41,17 @@ def test_status_strings_and_version():
 
 
 FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+LAB = ctypes.c_void_p(1 << 40)  # a label buffer far from FAKE (no overlap)
 
 
 @pytest.mark.parametrize("args,code", [
-    ((None, 4, 4, 4, 8, FAKE, None), 1),        # null image
+    ((None, 4, 4, 4, 8, LAB, None), 1),        # null image
     ((FAKE, 4, 4, 4, 8, None, None), 1),        # null labels
-    ((FAKE, 0, 4, 4, 8, FAKE, None), 1),        # H = 0
-    ((FAKE, 4, -1, 4, 8, FAKE, None), 1),       # W < 0
-    ((FAKE, 4, 8, 7, 8, FAKE, None), 1),        # pitch < W
-    ((FAKE, 4, 4, 4, 6, FAKE, None), 2),        # connectivity 6
-    ((FAKE, 65536, 65537, 65537, 8, FAKE, None), 3),  # H*W > 2^32-1
+    ((FAKE, 0, 4, 4, 8, LAB, None), 1),        # H = 0
+    ((FAKE, 4, -1, 4, 8, LAB, None), 1),       # W < 0
+    ((FAKE, 4, 8, 7, 8, LAB, None), 1),        # pitch < W
+    ((FAKE, 4, 4, 4, 6, LAB, None), 2),        # connectivity 6
+    ((FAKE, 65536, 65537, 65537, 8, LAB, None), 3),  # H*W > 2^32-1
 ])
 def test_invalid_arguments(args, code):
     lib = binding.load_library()
@@ -58,11 +59,11 @@ def test_invalid_arguments(args, code):
 
 
 @pytest.mark.parametrize("args,code", [
-    ((None, 4, 4, 4, 8, FAKE, None, None), 1),        # null image
+    ((None, 4, 4, 4, 8, LAB, None, None), 1),        # null image
     ((FAKE, 4, 4, 4, 8, None, None, None), 1),        # null labels
-    ((FAKE, 4, 8, 7, 8, FAKE, None, None), 1),        # pitch < W
-    ((FAKE, 4, 4, 4, 6, FAKE, None, None), 2),        # connectivity 6
-    ((FAKE, 65536, 65537, 65537, 8, FAKE, None, None), 3),  # H*W > 2^32-1
+    ((FAKE, 4, 8, 7, 8, LAB, None, None), 1),        # pitch < W
+    ((FAKE, 4, 4, 4, 6, LAB, None, None), 2),        # connectivity 6
+    ((FAKE, 65536, 65537, 65537, 8, LAB, None, None), 3),  # H*W > 2^32-1
 ])
 def test_equal_invalid_arguments(args, code):
     lib = binding.load_library()
@@ -74,16 +75,16 @@ def test_equal_config_validation():
     lib = binding.load_library()
     for th, nw in ((64, 1), (64, 16), (16, 1), (48, 4)):
         cfg = binding.Config(th, nw)
-        assert lib.ccl_label_2d_equal(FAKE, 64, 64, 64, 8, FAKE, ctypes.byref(cfg), None) == 2
+        assert lib.ccl_label_2d_equal(FAKE, 64, 64, 64, 8, LAB, ctypes.byref(cfg), None) == 2
 
 
 @pytest.mark.parametrize("args,code", [
-    ((None, 2, 4, 4, 4, 16, 26, FAKE, None), 1),          # null volume
-    ((FAKE, 0, 4, 4, 4, 16, 26, FAKE, None), 1),          # D = 0
-    ((FAKE, 2, 4, 8, 7, 32, 26, FAKE, None), 1),          # pitch_y < W
-    ((FAKE, 2, 4, 8, 8, 31, 26, FAKE, None), 1),          # pitch_z < H * pitch_y
-    ((FAKE, 2, 4, 4, 4, 16, 8, FAKE, None), 2),           # connectivity 8
-    ((FAKE, 2048, 2048, 2048, 2048, 2048 * 2048, 6, FAKE, None), 3),  # D*H*W > 2^32-1
+    ((None, 2, 4, 4, 4, 16, 26, LAB, None), 1),          # null volume
+    ((FAKE, 0, 4, 4, 4, 16, 26, LAB, None), 1),          # D = 0
+    ((FAKE, 2, 4, 8, 7, 32, 26, LAB, None), 1),          # pitch_y < W
+    ((FAKE, 2, 4, 8, 8, 31, 26, LAB, None), 1),          # pitch_z < H * pitch_y
+    ((FAKE, 2, 4, 4, 4, 16, 8, LAB, None), 2),           # connectivity 8
+    ((FAKE, 2048, 2048, 2048, 2048, 2048 * 2048, 6, LAB, None), 3),  # D*H*W > 2^32-1
 ])
 def test_3d_invalid_arguments(args, code):
     lib = binding.load_library()
@@ -93,14 +94,14 @@ def test_3d_invalid_arguments(args, code):
 def test_ex_validation():
     lib = binding.load_library()
     cfg = binding.Config(48, 4)
-    assert lib.ccl_label_2d_ex(FAKE, 64, 64, 64, 8, FAKE, None, 0, ctypes.byref(cfg), None) == 2
+    assert lib.ccl_label_2d_ex(FAKE, 64, 64, 64, 8, LAB, None, 0, ctypes.byref(cfg), None) == 2
     cfg = binding.Config(64, 3)
-    assert lib.ccl_label_2d_ex(FAKE, 64, 64, 64, 8, FAKE, None, 0, ctypes.byref(cfg), None) == 2
+    assert lib.ccl_label_2d_ex(FAKE, 64, 64, 64, 8, LAB, None, 0, ctypes.byref(cfg), None) == 2
     # caller workspace too small / misaligned
-    assert lib.ccl_label_2d_ex(FAKE, 64, 64, 64, 8, FAKE, FAKE, 16, None, None) == 7
+    assert lib.ccl_label_2d_ex(FAKE, 64, 64, 64, 8, LAB, FAKE, 16, None, None) == 7
     big = binding.workspace_size(64, 64)
     odd = ctypes.c_void_p(0x1001)
-    assert lib.ccl_label_2d_ex(FAKE, 64, 64, 64, 8, FAKE, odd, big, None, None) == 1
+    assert lib.ccl_label_2d_ex(FAKE, 64, 64, 64, 8, LAB, odd, big, None, None) == 1
 
 
 def test_workspace_size_formula():
@@ -133,8 +134,8 @@ def test_autotune_validation_without_device():
     lib = binding.load_library()
     best = binding.Config(0, 0)
     assert lib.ccl_autotune(None, 8, 8, 8, 8, FAKE, 3, None, ctypes.byref(best), None) == 1
-    assert lib.ccl_autotune(FAKE, 8, 8, 8, 5, FAKE, 3, None, ctypes.byref(best), None) == 2
-    assert lib.ccl_autotune(FAKE, 8, 8, 8, 8, FAKE, 0, None, ctypes.byref(best), None) == 1
+    assert lib.ccl_autotune(FAKE, 8, 8, 8, 5, LAB, 3, None, ctypes.byref(best), None) == 2
+    assert lib.ccl_autotune(FAKE, 8, 8, 8, 8, LAB, 0, None, ctypes.byref(best), None) == 1
 
 
 def test_tuning_table_roundtrip(tmp_path):
@@ -161,14 +162,14 @@ def test_tuning_table_roundtrip(tmp_path):
 
 
 @pytest.mark.parametrize("args,code", [
-    ((None, 4, 4, 4, 8, FAKE, None), 1),        # null image
+    ((None, 4, 4, 4, 8, LAB, None), 1),        # null image
     ((FAKE, 4, 4, 4, 8, None, None), 1),        # null labels
-    ((FAKE, 0, 4, 4, 8, FAKE, None), 1),        # H = 0
-    ((FAKE, 4, 8, 7, 8, FAKE, None), 1),        # pitch < W
-    ((FAKE, 4, 4, 4, 6, FAKE, None), 2),        # connectivity 6
-    ((FAKE, 65536, 65537, 65537, 8, FAKE, None), 3),  # H*W > 2^32-1
-    ((FAKE, 8192, 8192, 8192, 8, FAKE, None), 7),     # needs more than the fixed array
-    ((FAKE, 1, 60000000, 60000000, 4, FAKE, None), 7),
+    ((FAKE, 0, 4, 4, 8, LAB, None), 1),        # H = 0
+    ((FAKE, 4, 8, 7, 8, LAB, None), 1),        # pitch < W
+    ((FAKE, 4, 4, 4, 6, LAB, None), 2),        # connectivity 6
+    ((FAKE, 65536, 65537, 65537, 8, LAB, None), 3),  # H*W > 2^32-1
+    ((FAKE, 8192, 8192, 8192, 8, LAB, None), 7),     # needs more than the fixed array
+    ((FAKE, 1, 60000000, 60000000, 4, LAB, None), 7),
 ])
 def test_noalloc_invalid_arguments(args, code):
     """The fixed-workspace entry point rejects bad arguments, and images
@@ -195,14 +196,14 @@ def test_ctx_autotune_validation_without_device():
 
 
 @pytest.mark.parametrize("args,code", [
-    ((None, 4, 4, 4, 8, FAKE, FAKE, 1, FAKE, None, None), 1),      # null image
+    ((None, 4, 4, 4, 8, LAB, FAKE, 1, FAKE, None, None), 1),      # null image
     ((FAKE, 4, 4, 4, 8, None, FAKE, 1, FAKE, None, None), 1),      # null labels
-    ((FAKE, 4, 4, 4, 8, FAKE, FAKE, 1, None, None, None), 1),      # null count
-    ((FAKE, 4, 4, 4, 8, FAKE, None, 1, FAKE, None, None), 1),      # capacity without records
-    ((FAKE, 4, 4, 4, 8, FAKE, FAKE, -1, FAKE, None, None), 1),     # capacity < 0
-    ((FAKE, 4, 8, 7, 8, FAKE, FAKE, 1, FAKE, None, None), 1),      # pitch < W
-    ((FAKE, 4, 4, 4, 6, FAKE, FAKE, 1, FAKE, None, None), 2),      # connectivity 6
-    ((FAKE, 65536, 65537, 65537, 8, FAKE, FAKE, 1, FAKE, None, None), 3),  # H*W > 2^32-1
+    ((FAKE, 4, 4, 4, 8, LAB, FAKE, 1, None, None, None), 1),      # null count
+    ((FAKE, 4, 4, 4, 8, LAB, None, 1, FAKE, None, None), 1),      # capacity without records
+    ((FAKE, 4, 4, 4, 8, LAB, FAKE, -1, FAKE, None, None), 1),     # capacity < 0
+    ((FAKE, 4, 8, 7, 8, LAB, FAKE, 1, FAKE, None, None), 1),      # pitch < W
+    ((FAKE, 4, 4, 4, 6, LAB, FAKE, 1, FAKE, None, None), 2),      # connectivity 6
+    ((FAKE, 65536, 65537, 65537, 8, LAB, FAKE, 1, FAKE, None, None), 3),  # H*W > 2^32-1
 ])
 def test_label_stats_invalid_arguments(args, code):
     """The labels-with-statistics entry point validates like ccl_label_2d
@@ -216,4 +217,30 @@ def test_label_stats_config_validation():
     lib = binding.load_library()
     for th, nw in ((128, 4), (128, 8), (48, 4), (64, 3)):
         cfg = binding.Config(th, nw)
-        assert lib.ccl_label_2d_stats(FAKE, 64, 64, 64, 8, FAKE, FAKE, 1, FAKE, ctypes.byref(cfg), None) == 2
+        assert lib.ccl_label_2d_stats(FAKE, 64, 64, 64, 8, LAB, FAKE, 1, FAKE, ctypes.byref(cfg), None) == 2
+
+
+def test_overlapping_image_and_labels_are_rejected():
+    """Image and label bytes that intersect are an invalid argument, for
+    every entry point that takes both; adjacent buffers are fine."""
+    lib = binding.load_library()
+    img = 0x100000
+    H, W, pitch = 16, 20, 32
+    end = img + (H - 1) * pitch + W                     # one past the image's last byte
+    inside = ctypes.c_void_p(img + 8)
+    assert lib.ccl_label_2d(ctypes.c_void_p(img), H, W, pitch, 8, inside, None) == 1
+    assert lib.ccl_label_2d(ctypes.c_void_p(img), H, W, pitch, 8, ctypes.c_void_p(end - 1), None) == 1
+    below = ctypes.c_void_p(img - H * W * 4 + 4)        # labels ending inside the image
+    assert lib.ccl_label_2d(ctypes.c_void_p(img), H, W, pitch, 8, below, None) == 1
+    # adjacent on either side: validation passes (connectivity 6 is the error)
+    assert lib.ccl_label_2d(ctypes.c_void_p(img), H, W, pitch, 6, ctypes.c_void_p(end), None) == 2
+    assert lib.ccl_label_2d(ctypes.c_void_p(img), H, W, pitch, 6, ctypes.c_void_p(img - H * W * 4), None) == 2
+    assert lib.ccl_label_2d_equal(ctypes.c_void_p(img), H, W, pitch, 8, inside, None, None) == 1
+    assert lib.ccl_label_2d_ex(ctypes.c_void_p(img), H, W, pitch, 8, inside, None, 0, None, None) == 1
+    assert lib.ccl_label_2d_noalloc(ctypes.c_void_p(img), H, W, pitch, 8, inside, None) == 1
+    assert lib.ccl_label_2d_stats(ctypes.c_void_p(img), H, W, pitch, 8, inside, LAB, 1, FAKE, None, None) == 1
+    # a volume: D slices of H rows
+    D, py, pz = 3, 32, 16 * 32
+    vend = img + (D - 1) * pz + (H - 1) * py + W
+    assert lib.ccl_label_3d(ctypes.c_void_p(img), D, H, W, py, pz, 26, ctypes.c_void_p(vend - 4), None) == 1
+    assert lib.ccl_label_3d(ctypes.c_void_p(img), D, H, W, py, pz, 8, ctypes.c_void_p(vend), None) == 2
