@@ -671,8 +671,15 @@ __device__ __forceinline__ void sweep_bands(uint32_t *par, const uint64_t *msk, 
                     if (r0) key_link(par, md, o0);
                     if (r1) key_link(par, md, o1);
                 }
-                if (in) md = key_root(par, md);
-                if (lane_in(S)) lds_st(pn, md);
+                // under 8-connectivity the walk to the current root pays:
+                // dense images link many roots per band, and carrying a
+                // root that was just linked elsewhere deepens the trees the
+                // next bands walk; under 4-connectivity it does not pay
+                // (measured), and key_link tolerates a stale root
+                if (CONN8) {
+                    if (in) md = key_root(par, md);
+                    if (lane_in(S)) lds_st(pn, md);
+                }
             }
         } else if (in) {
             md = lds_ld(pn);
