@@ -321,52 +321,62 @@ constexpr uint32_t kBandGroupTiles = 16;
 // Workgroup (b, g): tile row b, tile columns [16 g, 16 g + 16).  Every
 // workgroup of the row scans the whole row's words (their ranks depend on
 // the words to their left in every image row of the tile row) and keeps
-// the part of its columns.
+// the part of its columns; the counts it needs are all loaded up front, and
+// the ranks of its own words stay in LDS for its records.
 template <int TH, bool CONN8>
 __global__ void __launch_bounds__(1024) st_band(ImgView v, StatsView s) {
     constexpr int RMAX = stats_rmax(TH, CONN8);
     constexpr uint32_t NT = 1024;
-    __shared__ uint32_t part[16];
-    __shared__ uint32_t above;
+    constexpr uint32_t GW = (uint32_t)TH * kBandGroupTiles;  // the group's row words
+    __shared__ uint32_t part[2][16];
+    __shared__ uint32_t gpre[kBandGroupTiles + 1];
+    __shared__ uint64_t gcm[GW];
+    __shared__ uint32_t gbase[GW];
     const uint32_t TX = (uint32_t)v.tilesX, TY = (uint32_t)v.tilesY, H = (uint32_t)v.H, W = (uint32_t)v.W;
     const uint32_t ng = (TX + kBandGroupTiles - 1u) / kBandGroupTiles;
     const uint32_t b = blockIdx.x / ng, g = blockIdx.x % ng;
-    const uint32_t gx0 = g * kBandGroupTiles, gx1 = min(TX, gx0 + kBandGroupTiles);
+    const uint32_t gx0 = g * kBandGroupTiles, gx1 = min(TX, gx0 + kBandGroupTiles), gn = gx1 - gx0;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    // components whose roots lie in the tile rows above
-    uint32_t acc = 0;
-    for (uint32_t i = tid; i < b * TX; i += NT) acc += s.tcnt[i];
-    acc = wave_sum_u32(acc);
-    if (lane == 0) part[wave] = acc;
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t a = 0;
-        for (int j = 0; j < 16; ++j) a += part[j];
-        above = a;
-    }
-    __syncthreads();
-    // the tile row's words are consecutive in raster order
+    // the tile row's words are consecutive in raster order; this thread's
+    // share of them, the components of the tile rows above, and the group's
+    // record counts, loaded together
     const uint32_t y0 = b * (uint32_t)TH, y1 = min(H, y0 + (uint32_t)TH);
     const size_t w0 = (size_t)y0 * TX;
     const uint32_t nw = (y1 - y0) * TX;
     const uint32_t per = (nw + NT - 1u) / NT;
     const uint32_t a0 = min(nw, tid * per), a1 = min(nw, a0 + per);
-    uint32_t c = 0;
+    uint32_t acc = 0, c = 0;
+    for (uint32_t i = tid; i < b * TX; i += NT) acc += s.tcnt[i];
     for (uint32_t w = a0; w < a1; ++w) c += (uint32_t)__popcll(s.cm[w0 + w]);
+    const uint32_t nrec = wave == 0 && lane < gn ? s.ncnt[b * TX + gx0 + lane] & 0xFFFFu : 0u;
+    acc = wave_sum_u32(acc);
     uint32_t wtot;
     const uint32_t ex = wave_exclusive_scan(c, &wtot);
-    if (lane == 0) part[wave] = wtot;
-    __syncthreads();
-    uint32_t run = above + ex, total = 0;
-    for (uint32_t j = 0; j < 16u; ++j) {
-        if (j < wave) run += part[j];
-        total += part[j];
+    if (lane == 0) {
+        part[0][wave] = acc;
+        part[1][wave] = wtot;
     }
+    if (wave == 0) {
+        uint32_t tot;
+        const uint32_t p = wave_exclusive_scan(nrec, &tot);
+        if (lane <= gn) gpre[lane] = lane < gn ? p : tot;
+    }
+    __syncthreads();
+    uint32_t above = 0, run = ex, total = 0;
+    for (uint32_t j = 0; j < 16u; ++j) {
+        above += part[0][j];
+        if (j < wave) run += part[1][j];
+        total += part[1][j];
+    }
+    run += above;
     for (uint32_t w = a0; w < a1; ++w) {
         const size_t gw = w0 + w;
         const uint64_t m = s.cm[gw];
         const uint32_t wx = (uint32_t)(gw % TX);
         if (wx >= gx0 && wx < gx1) {
+            const uint32_t li = (w / TX) * kBandGroupTiles + (wx - gx0);
+            gcm[li] = m;
+            gbase[li] = run;
             s.base[gw] = run;
             // components that reach a tile edge collect several records:
             // their output records start empty
@@ -395,15 +405,7 @@ __global__ void __launch_bounds__(1024) st_band(ImgView v, StatsView s) {
     // components inside one tile: their single record is final.  The
     // group's records are numbered across its tiles (a prefix of their
     // counts), so all threads take part whatever the tiles hold.
-    __shared__ uint32_t gpre[kBandGroupTiles + 1];
-    const uint32_t gn = gx1 - gx0;
-    if (wave == 0) {
-        const uint32_t n = lane < gn ? s.ncnt[b * TX + gx0 + lane] & 0xFFFFu : 0u;
-        uint32_t tot;
-        const uint32_t p = wave_exclusive_scan(n, &tot);
-        if (lane <= gn) gpre[lane] = lane < gn ? p : tot;
-    }
-    __syncthreads();  // also: this workgroup's base words are written
+    __syncthreads();
     const uint32_t nall = gpre[gn];
     for (uint32_t j = tid; j < nall; j += NT) {
         uint32_t k = 0;
@@ -411,8 +413,8 @@ __global__ void __launch_bounds__(1024) st_band(ImgView v, StatsView s) {
         const uint32_t tx = gx0 + k, t = b * TX + tx;
         const uint4 r = s.rec[(size_t)t * RMAX + (j - gpre[k])];
         const uint32_t pos = (r.y >> 12) & 0xFFFu;
-        const size_t w = (size_t)(y0 + (pos >> 6)) * TX + tx;
-        const uint32_t rank = s.base[w] + (uint32_t)__popcll(s.cm[w] & ((1ull << (pos & 63u)) - 1ull));
+        const uint32_t li = (pos >> 6) * kBandGroupTiles + k;
+        const uint32_t rank = gbase[li] + (uint32_t)__popcll(gcm[li] & ((1ull << (pos & 63u)) - 1ull));
         if (rank >= s.cap) continue;
         const Part p = unpack(r, tx * (uint32_t)kTileW, y0);
         ccl_component o;
