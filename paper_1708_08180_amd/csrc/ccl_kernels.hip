@@ -2,17 +2,19 @@
 // their launchers.
 //
 //   local merge        Sec. II-A (Kernel 1): tile-local merge with coarse
-//                      labeling; writes the tile's edge masks and edge-cell
-//                      roots, its row masks and per-run records to the
+//                      labeling over two-row bands (equal-value: runs);
+//                      writes the tile's edge masks and edge-cell roots, its
+//                      row masks, band data and per-interval records to the
 //                      workspace, and seeds labels[root] = root + 1 for roots
 //                      whose component touches a shared tile edge.
 //   boundary analysis  Sec. II-B (Kernel 2): union-find on tile-edge cells
 //                      only, one wavefront per tile (its top and left
 //                      edges); the only phase with global atomics.
-//   link               Sec. II-C: reads each tile's row masks and run
-//                      records, resolves each edge-touching local root once
-//                      in the global forest and writes the dense output
-//                      labels (1 + root, 0 for background).
+//   link               Sec. II-C: reads each tile's row masks and records,
+//                      resolves each edge-touching local root once in the
+//                      global forest and writes the dense output labels
+//                      (1 + root, 0 for background); its per-tile body is in
+//                      ccl_link.h, shared with the statistics link.
 //
 // The per-tile bodies are device functions shared by the single-image
 // kernels (one workgroup per tile; four tiles per workgroup for the
