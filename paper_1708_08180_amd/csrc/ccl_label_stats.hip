@@ -19,8 +19,9 @@
 //                   component count, the output records of components inside
 //                   one tile (complete in their single record), and the
 //                   output records of the others, initialised.
-//   st_span         per tile row: the records of components that reach a
-//                   tile edge, reduced by label in LDS, then added to the
+//   st_span         per tile row (per 16 tiles of one under
+//                   4-connectivity): the records of components that reach
+//                   a tile edge, reduced by label in LDS, then added to the
 //                   output records with global atomics.
 #include <hip/hip_runtime.h>
 
@@ -448,6 +449,19 @@ __device__ __forceinline__ void add_global(ccl_component &o, const Part &p) {
 }
 
 constexpr int kSpanSlots = 2048;
+
+// Tiles of one tile row whose edge-reaching records one st_span workgroup
+// reduces.  Under 8-connectivity a whole tile row: a percolating component
+// has records in most tiles, and each workgroup adds its part to that
+// component's one output record with atomics.  Under 4-connectivity the
+// crossing components are many and small (a tile row's distinct labels
+// would overflow the table), so runs of 16 tiles (measured: 47 µs per
+// launch with whole rows, 26 with 32 tiles, 15 with 16 or 8, at 4096² p=0.5).
+template <bool CONN8>
+__host__ __device__ constexpr uint32_t span_tiles(uint32_t tiles_x) {
+    return CONN8 ? tiles_x : 16u;
+}
+
 constexpr uint32_t kEmpty = 0u;  // no component has label 0
 
 struct SpanLds {
@@ -458,12 +472,12 @@ struct SpanLds {
     uint32_t wpart[16];
 };
 
-// One workgroup per tile row: the records of its components that reach a
-// tile edge, reduced by label in an LDS hash table, then added to the
-// output records.  A component that crosses many tiles (one that
-// percolates) has a record in most of them: the wavefront's smallest label
-// is reduced across lanes first, so it costs one table update per
-// wavefront pass, and one set of global atomics per tile row.
+// One workgroup per span_tiles() tiles of a tile row: the records of their
+// components that reach a tile edge, reduced by label in an LDS hash table,
+// then added to the output records.  A component that crosses many tiles
+// (one that percolates) has a record in most of them: the wavefront's
+// smallest label is reduced across lanes first, so it costs one table
+// update per wavefront pass, and one set of global atomics per workgroup.
 template <int TH, bool CONN8>
 __global__ void __launch_bounds__(1024) st_span(ImgView v, StatsView s) {
     constexpr int RMAX = stats_rmax(TH, CONN8);
@@ -471,7 +485,8 @@ __global__ void __launch_bounds__(1024) st_span(ImgView v, StatsView s) {
     __shared__ SpanLds sh;
     const uint32_t TX = (uint32_t)v.tilesX, W = (uint32_t)v.W;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    const uint32_t ty = blockIdx.x;
+    const uint32_t per = span_tiles<CONN8>(TX), nch = (TX + per - 1u) / per;
+    const uint32_t ty = blockIdx.x / nch, cx = (blockIdx.x % nch) * per, cend = min(TX, cx + per);
     for (uint32_t i = tid; i < (uint32_t)kSpanSlots; i += NT) {
         sh.key[i] = kEmpty;
         sh.area[i] = 0u;
@@ -500,9 +515,9 @@ __global__ void __launch_bounds__(1024) st_span(ImgView v, StatsView s) {
         if (rank < s.cap) add_global(s.out[rank], p);
     };
     __syncthreads();
-    for (uint32_t c0 = 0; c0 < TX; c0 += NT) {
-        // the next (at most 1024) tiles of the row: prefix of their counts
-        const uint32_t tcount = min(NT, TX - c0);
+    for (uint32_t c0 = cx; c0 < cend; c0 += NT) {
+        // the next (at most 1024) tiles: prefix of their counts
+        const uint32_t tcount = min(NT, cend - c0);
         const uint32_t mine = tid < tcount ? s.ncnt[ty * TX + c0 + tid] >> 16 : 0u;
         uint32_t wtot;
         const uint32_t ex = wave_exclusive_scan(mine, &wtot);
@@ -595,7 +610,9 @@ hipError_t launch_stats_t(const ImgView &v, const StatsView &s, hipStream_t st) 
     const uint32_t ng = ((uint32_t)v.tilesX + kBandGroupTiles - 1u) / kBandGroupTiles;
     hipLaunchKernelGGL((k3_link_stats<TH, CONN8>), dim3(tiles), dim3(stats_waves<TH>() * 64), 0, st, v, s);
     hipLaunchKernelGGL((st_band<TH, CONN8>), dim3((uint32_t)v.tilesY * ng), dim3(1024), 0, st, v, s);
-    hipLaunchKernelGGL((st_span<TH, CONN8>), dim3((uint32_t)v.tilesY), dim3(1024), 0, st, v, s);
+    const uint32_t per = span_tiles<CONN8>((uint32_t)v.tilesX);
+    hipLaunchKernelGGL((st_span<TH, CONN8>), dim3((uint32_t)v.tilesY * (((uint32_t)v.tilesX + per - 1u) / per)),
+                       dim3(1024), 0, st, v, s);
     return hipGetLastError();
 }
 
