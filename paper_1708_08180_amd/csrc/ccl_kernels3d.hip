@@ -6,7 +6,8 @@
 //                 for 6-connectivity, 8 for 18 and 26); every run then takes
 //                 its slice root, and every row is joined with the rows of
 //                 the previous slice it touches (pair masks, one LDS
-//                 atomicMin per pair of roots).  Every foreground
+//                 atomicMin per pair of roots; the four wavefronts share
+//                 these joins by rows).  Every foreground
 //                 voxel gets labels[p] = 1 + its tile-local root (a dense
 //                 store, as in the paper's Kernel 1), which is already a
 //                 valid forest.
@@ -112,16 +113,20 @@ __global__ void __launch_bounds__(256) k1_local_merge3d(Vol v) {
     // the slice merges below start from roots
     compress_nodes(par, msk, tid);
     __syncthreads();
-    if (wave > 0) {
-        // rows of slice w against the rows of slice w-1 they touch: the
+    {
+        // rows of slice z against the rows of slice z-1 they touch: the
         // straight row (with diagonals unless 6-connectivity) and, for 18 /
         // 26, the rows above and below it (straight / with diagonals).  The
         // roots of all upper runs a lane touches are read together and
         // joined with its own run's root by one atomicMin each; only a join
         // whose root was linked elsewhere meanwhile continues as a walk.
+        // Wavefront w takes rows 4w .. 4w+3 of every slice pair, so all
+        // four share the joins.
         constexpr int NQ = CONN == 6 ? 1 : 6;
-        for (int yi = 0; yi < kTY; ++yi) {
-            const int r = wave * kTY + yi, ru = (wave - 1) * kTY + yi;
+        constexpr int RJ = kTY / 4;
+        for (int j = 0; j < (kTZ - 1) * RJ; ++j) {
+            const int sz = 1 + j / RJ, yi = wave * RJ + j % RJ;
+            const int r = sz * kTY + yi, ru = (sz - 1) * kTY + yi;
             const uint64_t d = uniform64(msk[r]);
             const uint64_t S = run_starts(d);
             const bool fg = lane_in(d);
