@@ -458,6 +458,13 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Lane k's value of x (k wave-uniform), in scalar registers.
+__device__ __forceinline__ uint64_t lane_value64(uint64_t x, int k) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), k);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Which (lower run, upper run) pairs of two adjacent lines are merged, as
 // lane masks over the lower line d with the upper line u: every pair of runs
 // that touch is taken exactly once, by the leftmost lower cell adjacent to

@@ -456,11 +456,9 @@ __global__ void __launch_bounds__(256) k2_boundary(ImgView v, uint32_t tiles) {
 template <int TH, int NW, bool EQ>
 __global__ void __launch_bounds__(NW * 64) k3_link(ImgView v) {
     __shared__ uint32_t fin[TH * kTileW];
-    __shared__ uint16_t flist[NW * roots_per_tile(TH)];
     constexpr int SPR = slots_per_row<EQ>();
     const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
-    k3_tile<TH, NW, EQ>(v, t, v.rowmask + (size_t)t * rowmask_words(TH), v.slots + (size_t)t * TH * SPR,
-                        fin, flist);
+    k3_tile<TH, NW, EQ>(v, t, v.rowmask + (size_t)t * rowmask_words(TH), v.slots + (size_t)t * TH * SPR, fin);
 }
 
 // ------------------------------------------------------------ batch kernels
@@ -511,12 +509,11 @@ __global__ void __launch_bounds__(256) k2_batch(BatchArgs a) {
 template <int TH, int NW>
 __global__ void __launch_bounds__(NW * 64) k3_batch(BatchArgs a) {
     __shared__ uint32_t fin[TH * kTileW];
-    __shared__ uint16_t flist[NW * roots_per_tile(TH)];
     const uint32_t g = xcd_remap(blockIdx.x, gridDim.x);
     if (g >= a.tiles) return;  // workgroup-uniform
     const BatchImage &d = a.descs[a.w.tile_img[g]];
     k3_tile<TH, NW, false>(batch_view<TH>(d, a.w), g - d.tile_base, a.w.rowmask + (size_t)g * rowmask_words(TH),
-                           a.w.slots + (size_t)g * TH * kSlotsPerRow, fin, flist);
+                           a.w.slots + (size_t)g * TH * kSlotsPerRow, fin);
 }
 
 // ---------------------------------------------------------------- launchers

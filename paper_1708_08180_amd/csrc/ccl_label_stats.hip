@@ -91,7 +91,6 @@ struct StatsLds {
     // 8-connectivity (runs), 64 under 4-connectivity
     static constexpr int ILIST = RPW / 2 * (CONN8 ? 32 : 64);
     uint32_t fin[TH * kTileW];
-    uint16_t flist[NW * roots_per_tile(TH)];
     uint64_t rows[TH];                    // foreground per row
     uint64_t frows[TH];                   // flagged local roots per row
     uint64_t bends[TH / 2];               // band interval ends
@@ -108,7 +107,6 @@ struct StatsLds {
 template <int TH, bool CONN8>
 __global__ void __launch_bounds__(stats_waves<TH>() * 64) k3_link_stats(ImgView v, StatsView s) {
     constexpr int NW = stats_waves<TH>(), NT = NW * 64;
-    constexpr int kFlagCap = roots_per_tile(TH);
     using LR = LinkRows<TH, NW, false>;
     constexpr int RPW = LR::RPW, BPW = LR::BPW;
     using Lds = StatsLds<TH, CONN8>;
@@ -139,7 +137,7 @@ __global__ void __launch_bounds__(stats_waves<TH>() * 64) k3_link_stats(ImgView 
         sh.ym[i] = 0ull;
     }
     LR R;
-    k3_resolve<TH, NW, false>(v, t, rw, v.slots + (size_t)t * TH * kSlotsPerRow, sh.fin, sh.flist, R);
+    k3_resolve<TH, NW, false>(v, t, rw, v.slots + (size_t)t * TH * kSlotsPerRow, sh.fin, R);
     const int lane = tid & 63, wave = R.wave;
     const uint32_t W = (uint32_t)v.W, TX = (uint32_t)v.tilesX;
     const uint32_t tx = R.tx, ty = R.ty;
@@ -149,13 +147,13 @@ __global__ void __launch_bounds__(stats_waves<TH>() * 64) k3_link_stats(ImgView 
     // flagged local roots that stayed roots of the forest are their
     // component's root (unflagged local roots always are)
     {
-        uint32_t nf = 0;
-        for (int k = 0; k < RPW; ++k) nf += (uint32_t)__popcll(uniform64(sh.frows[wave * RPW + k]));
-        nf = min(nf, (uint32_t)kFlagCap);
-        const uint16_t *fl = sh.flist + wave * kFlagCap;
-        for (uint32_t i = (uint32_t)lane; i < nf; i += 64u) {
-            const uint32_t l = fl[i];
-            if (sh.fin[l] == origin + (l >> 6) * W + (l & 63u)) atomicOr(&sh.fcm[l >> 6], 1ull << (l & 63u));
+        const uint64_t fv = lane < RPW ? sh.frows[wave * RPW + lane] : 0ull;
+        uint32_t nf;
+        const uint32_t fpre = wave_exclusive_scan((uint32_t)__popcll(fv), &nf);
+        for (uint32_t b = 0; b < nf; b += 64u) {  // wave-uniform
+            const uint32_t i = b + (uint32_t)lane;
+            const uint32_t l = (uint32_t)(wave * RPW * kTileW) + nth_flagged<RPW>(fv, fpre, i);
+            if (i < nf && sh.fin[l] == origin + (l >> 6) * W + (l & 63u)) atomicOr(&sh.fcm[l >> 6], 1ull << (l & 63u));
         }
     }
     // local roots: the pixels that are their own interval's root

@@ -7,13 +7,11 @@
 // local root pixel first puts its final label - 1 into fin[]: unflagged
 // roots are already final; flagged roots are resolved in the global forest
 // (where a tile's stores of final labels compress the paths of the tiles
-// that still walk through its pixels).  A wavefront lists the flagged roots
-// of its rows in LDS and resolves them all at once, one per lane, so their
-// walks overlap instead of following each other row by row.  Then every
-// pixel reads its root's entry; output rows are full 256-byte lines.
-//
-// A flagged root is the root of some edge cell, so a tile has at most
-// roots_per_tile(TH) of them; `flist` holds that many entries per wavefront.
+// that still walk through its pixels).  A wavefront resolves all flagged
+// roots of its rows at once, lane i the i-th in row order (found from the
+// rows' flag masks, with no list in LDS), so their walks overlap instead of
+// following each other row by row.  Then every pixel reads its root's
+// entry; output rows are full 256-byte lines.
 #pragma once
 
 #include "ccl_device.h"
@@ -31,12 +29,53 @@ struct LinkRows {
     // of the band share (binary)
     static constexpr int NR = EQ ? RPW : BPW;
     uint64_t m[RPW];   // row foreground (equal-value: run starts)
-    uint64_t f[RPW];   // flagged local roots of the row
     uint64_t be[BPW];  // band interval ends (binary)
     uint32_t rec[NR];  // this lane's tile-local root pixel, kNone for background
     uint32_t tx, ty;   // the tile's position in the tile grid
     int wave;          // this wavefront (wave-uniform)
 };
+
+// Offset (row << 6 | column, rows counted from the wavefront's first) of
+// the i-th flagged local root, in row order, of a wavefront's RPW rows.  fv:
+// lane k < RPW holds row k's flag mask, other lanes 0; fpre: the exclusive
+// prefix count of fv's bits over the lanes.  The row is the last one whose
+// prefix is at most i (a binary search over the lanes), the column a binary
+// search by halves.  Call with every lane active (values move between
+// lanes); a lane whose i is at or past the total gets some offset inside
+// the rows.
+template <int RPW>
+__device__ __forceinline__ uint32_t nth_flagged(uint64_t fv, uint32_t fpre, uint32_t i) {
+    static_assert((RPW & (RPW - 1)) == 0 && RPW <= 64, "a power of two up to the wave size");
+    uint32_t row = 0, before = 0;
+#pragma unroll
+    for (int h = RPW / 2; h >= 1; h >>= 1) {
+        const uint32_t p = (uint32_t)__shfl((int)fpre, (int)row + h, 64);
+        if (i >= p) {
+            row += (uint32_t)h;
+            before = p;
+        }
+    }
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)fv, (int)row, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(fv >> 32), (int)row, 64);
+    uint32_t n = i - before;
+    uint32_t col = 0, w = lo;
+    const uint32_t c = (uint32_t)__builtin_popcount(lo);
+    if (n >= c) {
+        n -= c;
+        col = 32u;
+        w = hi;
+    }
+#pragma unroll
+    for (uint32_t h = 16u; h >= 1u; h >>= 1) {
+        const uint32_t ch = (uint32_t)__builtin_popcount(w & ((1u << h) - 1u));
+        if (n >= ch) {
+            n -= ch;
+            col += h;
+            w >>= h;
+        }
+    }
+    return row * (uint32_t)kTileW + col;
+}
 
 // First half of the link for tile t: loads the wavefront's rows and records
 // and fills fin[] for every local root of the tile.  Ends after a workgroup
@@ -45,10 +84,8 @@ struct LinkRows {
 // the image's descriptor in the batched form).
 template <int TH, int NW, bool EQ>
 __device__ __forceinline__ void k3_resolve(const ImgView &v, uint32_t t, const uint64_t *rw,
-                                           const uint16_t *sl, uint32_t *fin, uint16_t *flist,
-                                           LinkRows<TH, NW, EQ> &R) {
+                                           const uint16_t *sl, uint32_t *fin, LinkRows<TH, NW, EQ> &R) {
     using LR = LinkRows<TH, NW, EQ>;
-    constexpr int kFlagCap = roots_per_tile(TH);
     constexpr int SPR = slots_per_row<EQ>();
     constexpr int RPW = LR::RPW, BPW = LR::BPW, NR = LR::NR;
     const uint32_t TX = (uint32_t)v.tilesX;
@@ -78,10 +115,9 @@ __device__ __forceinline__ void k3_resolve(const ImgView &v, uint32_t t, const u
         rbv = lane < BPW ? (uint32_t)rbg[wave * BPW + lane] : 0u;
     }
 #pragma unroll
-    for (int k = 0; k < RPW; ++k) {
-        R.m[k] = uniform64(rm[k]);
-        R.f[k] = uniform64(rm[TH + k]);
-    }
+    for (int k = 0; k < RPW; ++k) R.m[k] = uniform64(rm[k]);
+    // flagged local roots of the rows, lane k holding row k's mask
+    const uint64_t fv = lane < RPW ? rm[TH + lane] : 0ull;
     if (!EQ) {
 #pragma unroll
         for (int k = 0; k < BPW; ++k) R.be[k] = uniform64(rw[rowmask_ends(TH) + wave * BPW + k]);
@@ -108,29 +144,19 @@ __device__ __forceinline__ void k3_resolve(const ImgView &v, uint32_t t, const u
         const uint32_t r = sl[node];
         R.rec[i] = lane_in(d) ? r : kNone;
     }
-    // this wave's flagged roots, listed in row order
-    uint16_t *fl = flist + wave * kFlagCap;
-    uint32_t nf = 0;
-#pragma unroll
-    for (int k = 0; k < RPW; ++k) {
-        const uint32_t pos = nf + bits_below(R.f[k]);
-        if (lane_in(R.f[k]) && pos < (uint32_t)kFlagCap)
-            fl[pos] = (uint16_t)((wave * RPW + k) * kTileW + lane);
-        nf += (uint32_t)__popcll(R.f[k]);
-    }
-    nf = min(nf, (uint32_t)kFlagCap);
     // unflagged local roots are final
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
         const uint32_t l = (uint32_t)((wave * RPW + k) * kTileW + lane);
-        if (R.rec[EQ ? k : k / 2] == l && !lane_in(R.f[k])) fin[l] = origin + (l >> 6) * W + (l & 63u);
+        if (R.rec[EQ ? k : k / 2] == l && !lane_in(lane_value64(fv, k))) fin[l] = origin + (l >> 6) * W + (l & 63u);
     }
-    // the list is read back by other lanes of this wavefront
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    for (uint32_t i = (uint32_t)lane; i < nf; i += 64u) {
-        const uint32_t l = fl[i];
-        fin[l] = g_root(v.labels, origin + (l >> 6) * W + (l & 63u));
+    // this wave's flagged roots
+    uint32_t nf;
+    const uint32_t fpre = wave_exclusive_scan((uint32_t)__popcll(fv), &nf);
+    for (uint32_t b = 0; b < nf; b += 64u) {  // wave-uniform
+        const uint32_t i = b + (uint32_t)lane;
+        const uint32_t l = (uint32_t)(wave * RPW * kTileW) + nth_flagged<RPW>(fv, fpre, i);
+        if (i < nf) fin[l] = g_root(v.labels, origin + (l >> 6) * W + (l & 63u));
     }
     __syncthreads();
 }
@@ -171,9 +197,9 @@ __device__ __forceinline__ void k3_write(const ImgView &v, const uint32_t *fin, 
 // The whole link for tile t.
 template <int TH, int NW, bool EQ>
 __device__ __forceinline__ void k3_tile(const ImgView &v, uint32_t t, const uint64_t *rw,
-                                        const uint16_t *sl, uint32_t *fin, uint16_t *flist) {
+                                        const uint16_t *sl, uint32_t *fin) {
     LinkRows<TH, NW, EQ> R;
-    k3_resolve<TH, NW, EQ>(v, t, rw, sl, fin, flist, R);
+    k3_resolve<TH, NW, EQ>(v, t, rw, sl, fin, R);
     k3_write<TH, NW, EQ>(v, fin, R);
 }
 
