@@ -74,8 +74,8 @@ def test_equal_closed_forms(conn):
 def test_equal_checkerboard_every_config(config):
     # 4-connectivity: every pixel is its own component, so every edge cell of
     # every tile is a root that the link pass resolves in the global forest
-    # (the fullest case of the per-wavefront list of such roots: a 64-cell
-    # top row plus the side cells of the band, more than one lane round)
+    # (the most such roots a link wavefront resolves: a 64-cell top row
+    # plus the side cells of its rows, more than one lane round)
     H, W = 200, 300
     cb = wl.checkerboard(H, W, 0, fg=5)
     say("equal checkerboard %dx%d config=%s" % (H, W, config))

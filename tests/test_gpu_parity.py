@@ -107,6 +107,20 @@ def test_tile_corner_patterns(conn):
             _cmp(img.astype(np.uint8), conn, config=(th, 4 if th >= 4 else 1), what="corners")
 
 
+@pytest.mark.parametrize("config", [c for c in CONFIGS if c[0] == 16] + [(64, 4), (128, 8)])
+def test_most_flagged_roots_per_link_wavefront(config):
+    """Under 4-connectivity a checkerboard makes every pixel its own
+    component, so every foreground edge cell is a flagged local root.  A
+    16-row link wavefront that holds both the top and the bottom row of a
+    16-row tile then has 32 + 32 + 7 + 7 = 78 of them, more than one per
+    lane (two rounds of walks); taller tiles give each wavefront at most
+    one of those rows."""
+    for phase in (0, 1):
+        img = wl.checkerboard(16 * 5 + 3, 64 * 3 + 7, phase)
+        _cmp(img, 4, config=config, what="checker%d-flagged" % phase)
+        _cmp(img, 8, config=config, what="checker%d-flagged" % phase)
+
+
 @pytest.mark.parametrize("conn", [8, 4])
 def test_long_chains(conn):
     for (H, W) in ((512, 512), (1000, 777)):
