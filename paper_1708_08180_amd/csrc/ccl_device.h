@@ -648,14 +648,15 @@ __device__ __forceinline__ void sweep_bands(uint32_t *par, const uint64_t *msk, 
         uint32_t *pn = &par[node];
         if (lane_in(S)) {
             // the interval's smallest pixel: its first top-row pixel, else
-            // its first pixel (a bottom-row one, at the start column); the
-            // first top-row pixel at or after the start belongs to the
-            // interval when no interval ends before it
-            const uint64_t tf = t & (~0ull << lane);
-            const uint64_t ft = tf & (0ull - tf);  // lowest bit of tf (0 if none)
-            const bool top = ft != 0ull && (E & (ft - 1ull) & (~0ull << lane)) == 0ull;
+            // its first pixel (a bottom-row one, at the start column).  Seen
+            // from the start column, the first top-row pixel belongs to the
+            // interval when it comes no later than the interval's end (the
+            // first end at or after the start, so er != 0)
+            const uint64_t tr = t >> lane, er = E >> lane;
+            const uint32_t dt = tr ? (uint32_t)__builtin_ctzll(tr) : 64u;
+            const bool top = dt <= (uint32_t)__builtin_ctzll(er);
             const uint32_t row = (uint32_t)(2 * band) + (top ? 0u : 1u);
-            const uint32_t col = top ? (uint32_t)__builtin_ctzll(ft) : (uint32_t)lane;
+            const uint32_t col = (uint32_t)lane + (top ? dt : 0u);
             lds_st(pn, (((row << 6) | col) << kNodeBits) | node);
         }
         uint32_t md = kNone;
