@@ -236,8 +236,10 @@ __device__ __forceinline__ void k1_tile_bands(const ImgView &v, uint32_t t, K1Ba
     }
     // edge masks and edge-cell roots for the boundary analysis; every such
     // root is seeded in the forest (lanes of one component store the same
-    // word) and marked in the edge-root masks
-    if (wave == 0) {
+    // word) and marked in the edge-root masks.  The four edges go to four
+    // wavefronts (edge k to wavefront k mod NW), so their root loads and
+    // stores overlap.
+    {
         uint64_t *mk = v.masks + (size_t)t * mask_words(TH);
         uint32_t *rt = v.roots + (size_t)t * roots_per_tile(TH);
         const uint64_t mTop = uniform64(msk[0]), mBot = uniform64(msk[TH - 1]);
@@ -253,36 +255,39 @@ __device__ __forceinline__ void k1_tile_bands(const ImgView &v, uint32_t t, K1Ba
         // first node of the last band, read while every lane is active (a
         // lane that is off inside the branch below may not hold it)
         const uint32_t bbLast = (uint32_t)__builtin_amdgcn_readlane((int)bbv, NB - 1);
-        if (hasUp && lane_in(mTop)) put(&rt[roots_top(TH) + lane], root_g(bits_below(uniform64(sh.ends[0]))));
-        if (hasDown && lane_in(mBot))
+        if (wave == 0) {
+            if (hasUp && lane_in(mTop)) put(&rt[roots_top(TH) + lane], root_g(bits_below(uniform64(sh.ends[0]))));
+            if (lane == 0) {
+                mk[kMaskTop] = mTop;
+                mk[kMaskBottom] = mBot;
+            }
+        }
+        if (wave == 1 % NW && hasDown && lane_in(mBot))
             put(&rt[roots_bottom(TH) + lane], root_g(bbLast + bits_below(uniform64(sh.ends[NB - 1]))));
         // per row (lane = row, 64 rows at a time): the band's first / last
         // interval holds the row's cell in the left / right column
+        if (wave == 2 % NW || wave == 3 % NW) {
 #pragma unroll
-        for (int h = 0; h < col_words(TH); ++h) {
-            const int r = 64 * h + lane;
-            const uint64_t mr = r < TH ? msk[r] : 0ull;
-            const bool lb = (mr & 1ull) != 0, rb = (mr >> 63) != 0;
-            const uint32_t bFirst = r < TH ? (uint32_t)sh.bbase[r >> 1] : 0u;
-            const uint32_t nInt = r < TH ? (uint32_t)__popcll(sh.ends[r >> 1]) : 0u;
-            const uint64_t mLeft = __ballot(lb), mRight = __ballot(rb);
-            if (hasLeft && lb) put(&rt[roots_left(TH) + r], root_g(bFirst));
-            if (hasRight && rb) put(&rt[roots_right(TH) + r], root_g(bFirst + nInt - 1u));
-            if (lane == 0) {
-                mk[kMaskLeft + h] = mLeft;
-                mk[mask_right(TH) + h] = mRight;
+            for (int h = 0; h < col_words(TH); ++h) {
+                const int r = 64 * h + lane;
+                const uint64_t mr = r < TH ? msk[r] : 0ull;
+                const bool lb = (mr & 1ull) != 0, rb = (mr >> 63) != 0;
+                const uint32_t bFirst = r < TH ? (uint32_t)sh.bbase[r >> 1] : 0u;
+                const uint32_t nInt = r < TH ? (uint32_t)__popcll(sh.ends[r >> 1]) : 0u;
+                const uint64_t mLeft = __ballot(lb), mRight = __ballot(rb);
+                if (wave == 2 % NW) {
+                    if (hasLeft && lb) put(&rt[roots_left(TH) + r], root_g(bFirst));
+                    if (lane == 0) mk[kMaskLeft + h] = mLeft;
+                }
+                if (wave == 3 % NW) {
+                    if (hasRight && rb) put(&rt[roots_right(TH) + r], root_g(bFirst + nInt - 1u));
+                    if (lane == 0) mk[mask_right(TH) + h] = mRight;
+                }
             }
         }
-        if (lane == 0) {
-            mk[kMaskTop] = mTop;
-            mk[kMaskBottom] = mBot;
-        }
-        // only this wavefront marks edge roots: once its own LDS operations
-        // have completed, the masks are whole
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        for (int r = lane; r < TH; r += 64) rw[TH + r] = flg[r];
     }
+    __syncthreads();  // every wavefront's marks are in
+    for (int r = tid; r < TH; r += NT) rw[TH + r] = flg[r];
     __syncthreads();  // LDS may be reused for another tile
 }
 
