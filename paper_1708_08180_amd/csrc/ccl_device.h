@@ -431,6 +431,14 @@ __device__ __forceinline__ uint32_t from_left(uint32_t v, uint32_t edge) {
 __device__ __forceinline__ uint32_t from_right(uint32_t v, uint32_t edge) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x130, 0xF, 0xF, false);
 }
+// The same shifts for callers that never read lane 0's / lane 63's result:
+// those lanes get 0 (one instruction, no edge value to set up).
+__device__ __forceinline__ uint32_t from_left_any(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint32_t from_right_any(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true);
+}
 
 __device__ __forceinline__ uint64_t run_starts(uint64_t d) { return d & ~(d << 1); }
 // last cell of every run
@@ -575,14 +583,26 @@ __device__ __forceinline__ void sweep_band(uint32_t *par, uint16_t *cr, const ui
 //
 // Node n of a tile is its n-th interval in band order, left to right inside
 // a band.  Every parent entry holds a key, the node's smallest pixel (tile
-// row << 6 | column) above its node number: an atomicMin on keys links the
-// tree whose node holds the larger pixel under the other, so the root of
-// every tree is the node holding the component's smallest pixel (the
-// linking rule of Sec. II-A-3, with pixels as the order).  A root's entry is
-// its own key.
+// row << 6 | column) above its node's byte offset in the parent array
+// (node << 2, so a key addresses its entry with one mask): an atomicMin on
+// keys links the tree whose node holds the larger pixel under the other, so
+// the root of every tree is the node holding the component's smallest pixel
+// (the linking rule of Sec. II-A-3, with pixels as the order).  A root's
+// entry is its own key.
 
-constexpr uint32_t kNodeBits = 12;  // at most 4096 nodes per tile (64 intervals per band)
-constexpr uint32_t kNodeMask = (1u << kNodeBits) - 1u;
+constexpr uint32_t kNodeBits = 14;  // at most 4096 nodes per tile (64 intervals per band)
+constexpr uint32_t kNodeMask = ((1u << 12) - 1u) << 2;
+
+// Key of node n whose smallest pixel is pos.
+__device__ __forceinline__ uint32_t node_key(uint32_t pos, uint32_t n) { return (pos << kNodeBits) | (n << 2); }
+
+// Parent entry of the node that key k names.
+__device__ __forceinline__ uint32_t *key_entry(uint32_t *par, uint32_t k) {
+    return (uint32_t *)((char *)par + (k & kNodeMask));
+}
+__device__ __forceinline__ const uint32_t *key_entry(const uint32_t *par, uint32_t k) {
+    return (const uint32_t *)((const char *)par + (k & kNodeMask));
+}
 
 // First column of every interval of the band (t above b).
 template <bool CONN8>
@@ -600,7 +620,7 @@ __device__ __forceinline__ uint64_t band_ends(uint64_t m, uint64_t s) { return m
 // Root key of the tree holding key k (read-only walk; see lds_root).
 __device__ __forceinline__ uint32_t key_root(const uint32_t *par, uint32_t k) {
     while (true) {
-        const uint32_t p = lds_ld(&par[k & kNodeMask]);
+        const uint32_t p = lds_ld(key_entry(par, k));
         if (p >= k) return k;
         k = p;
     }
@@ -611,7 +631,7 @@ __device__ __forceinline__ uint32_t key_root(const uint32_t *par, uint32_t k) {
 __device__ __forceinline__ void key_link(uint32_t *par, uint32_t a, uint32_t b) {
     while (a != b) {
         if (a > b) { const uint32_t t = a; a = b; b = t; }
-        const uint32_t old = atomicMin(&par[b & kNodeMask], a);
+        const uint32_t old = atomicMin(key_entry(par, b), a);
         if (old >= b) return;
         b = old;
     }
@@ -657,12 +677,13 @@ __device__ __forceinline__ void sweep_bands(uint32_t *par, const uint64_t *msk, 
             const bool top = dt <= (uint32_t)__builtin_ctzll(er);
             const uint32_t row = (uint32_t)(2 * band) + (top ? 0u : 1u);
             const uint32_t col = (uint32_t)lane + (top ? dt : 0u);
-            lds_st(pn, (((row << 6) | col) << kNodeBits) | node);
+            lds_st(pn, node_key((row << 6) | col, node));
         }
         uint32_t md = kNone;
         if (k > 0) {
             const PairMasks p = pair_masks<CONN8>(t, u);
-            const uint32_t rL = from_left(ra, kNone), rR = from_right(ra, kNone);
+            // PL never holds lane 0 and PR never lane 63 (no column beyond the tile)
+            const uint32_t rL = from_left_any(ra), rR = from_right_any(ra);
             const uint32_t t0 = lane_in(p.pm) ? ra : (lane_in(p.pl) ? rL : kNone);
             const uint32_t t1 = lane_in(p.pr) ? rR : kNone;
             const uint32_t tm = t0 < t1 ? t0 : t1;
@@ -672,8 +693,8 @@ __device__ __forceinline__ void sweep_bands(uint32_t *par, const uint64_t *msk, 
             const bool n1 = t1 != kNone && t1 != md;
             if (__ballot(n0 || n1)) {
                 uint32_t o0 = 0, o1 = 0;
-                if (n0) o0 = atomicMin(&par[t0 & kNodeMask], md);
-                if (n1) o1 = atomicMin(&par[t1 & kNodeMask], md);
+                if (n0) o0 = atomicMin(key_entry(par, t0), md);
+                if (n1) o1 = atomicMin(key_entry(par, t1), md);
                 const bool r0 = n0 && o0 < t0 && o0 != md, r1 = n1 && o1 < t1 && o1 != md;
                 if (__ballot(r0 || r1)) {
                     if (r0) key_link(par, md, o0);
