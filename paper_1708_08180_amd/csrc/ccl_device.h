@@ -590,7 +590,7 @@ __device__ __forceinline__ void sweep_band(uint32_t *par, uint16_t *cr, const ui
 // (the linking rule of Sec. II-A-3, with pixels as the order).  A root's
 // entry is its own key.
 
-constexpr uint32_t kNodeBits = 14;  // at most 4096 nodes per tile (64 intervals per band)
+constexpr uint32_t kNodeBits = 14;  // the byte offsets of at most 4096 nodes per tile (64 intervals per band)
 constexpr uint32_t kNodeMask = ((1u << 12) - 1u) << 2;
 
 // Key of node n whose smallest pixel is pos.
