@@ -58,12 +58,13 @@ struct StatsView {
 // pixels high and wide, so every field fits.  Records of components inside
 // the tile fill the tile's slots from the front, the others from the back.
 
-// Wavefronts of the statistics link: 8 rows each (with the 16 of the plain
-// link, the row masks held in scalar registers would not fit beside the
-// statistics' own state).
+// Wavefronts of the statistics link: 16 rows each, as in the plain link.
+// So that its scalar registers fit beside the statistics' own state, the
+// link keeps the band ends in a vector register and the local-id loop is
+// unrolled four rows at a time.
 template <int TH>
 constexpr int stats_waves() {
-    return TH / 8;
+    return TH / 16;
 }
 
 // Accumulators for this many local components at a time: a tile with more
@@ -137,7 +138,7 @@ __global__ void __launch_bounds__(stats_waves<TH>() * 64) k3_link_stats(ImgView 
         sh.ym[i] = 0ull;
     }
     LR R;
-    k3_resolve<TH, NW, false>(v, t, rw, v.slots + (size_t)t * TH * kSlotsPerRow, sh.fin, R);
+    k3_resolve<TH, NW, false, true>(v, t, rw, v.slots + (size_t)t * TH * kSlotsPerRow, sh.fin, R);
     const int lane = tid & 63, wave = R.wave;
     const uint32_t W = (uint32_t)v.W, TX = (uint32_t)v.tilesX;
     const uint32_t tx = R.tx, ty = R.ty;
@@ -190,7 +191,7 @@ __global__ void __launch_bounds__(stats_waves<TH>() * 64) k3_link_stats(ImgView 
     }
     // local ids in raster order; component roots per row word
     uint32_t ncomp = 0;
-#pragma unroll
+#pragma unroll 4
     for (int k = 0; k < RPW; ++k) {
         const int row = wave * RPW + k;
         const uint64_t rmk = uniform64(sh.rmask[row]), fk = uniform64(sh.frows[row]);

@@ -79,10 +79,12 @@ __device__ __forceinline__ uint32_t nth_flagged(uint64_t fv, uint32_t fpre, uint
 
 // First half of the link for tile t: loads the wavefront's rows and records
 // and fills fin[] for every local root of the tile.  Ends after a workgroup
-// barrier.  `rw` / `sl`: the tile's row data and run records in the
+// barrier.  LANE_ENDS: the band ends are held in a vector register (lane k:
+// band k) instead of scalar registers, for callers short of scalar
+// registers.  `rw` / `sl`: the tile's row data and run records in the
 // workspace (they depend on the tile only, so their loads need not wait for
 // the image's descriptor in the batched form).
-template <int TH, int NW, bool EQ>
+template <int TH, int NW, bool EQ, bool LANE_ENDS = false>
 __device__ __forceinline__ void k3_resolve(const ImgView &v, uint32_t t, const uint64_t *rw,
                                            const uint16_t *sl, uint32_t *fin, LinkRows<TH, NW, EQ> &R) {
     using LR = LinkRows<TH, NW, EQ>;
@@ -118,9 +120,14 @@ __device__ __forceinline__ void k3_resolve(const ImgView &v, uint32_t t, const u
     for (int k = 0; k < RPW; ++k) R.m[k] = uniform64(rm[k]);
     // flagged local roots of the rows, lane k holding row k's mask
     const uint64_t fv = lane < RPW ? rm[TH + lane] : 0ull;
+    uint64_t ev = 0ull;
     if (!EQ) {
+        if (LANE_ENDS) {
+            if (lane < BPW) ev = rw[rowmask_ends(TH) + wave * BPW + lane];
+        } else {
 #pragma unroll
-        for (int k = 0; k < BPW; ++k) R.be[k] = uniform64(rw[rowmask_ends(TH) + wave * BPW + k]);
+            for (int k = 0; k < BPW; ++k) R.be[k] = uniform64(rw[rowmask_ends(TH) + wave * BPW + k]);
+        }
     }
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
@@ -136,7 +143,7 @@ __device__ __forceinline__ void k3_resolve(const ImgView &v, uint32_t t, const u
             node = (uint32_t)__builtin_amdgcn_readlane((int)rbv, i) + (below ? below - 1u : 0u);
             d = i < rows_in ? cols : 0ull;
         } else {
-            const uint64_t E = R.be[i];
+            const uint64_t E = LANE_ENDS ? lane_value64(ev, i) : R.be[i];
             const uint32_t below = bits_below(E), last = (uint32_t)__popcll(E);
             node = (uint32_t)__builtin_amdgcn_readlane((int)rbv, i) + (below < last ? below : (last ? last - 1u : 0u));
             d = R.m[2 * i] | R.m[2 * i + 1];
